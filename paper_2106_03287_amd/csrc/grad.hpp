@@ -1,0 +1,82 @@
+// Per-particle mean point-to-point gradient (Eqs. 4-5), fused with the final
+// reduction of the per-chunk nearest-neighbour keys.
+//
+// One workgroup per particle. Each thread takes minibatch points i = tid,
+// tid + 256, ...: it reduces the chunk keys of its query to the matched
+// reference index, recomputes the FP64 transform s' = R s + u, forms the
+// residual e = s' - r and the six contributions e and e^T (dR/dtheta_d) s,
+// accumulating in FP64. The 256 partial sums are combined by a fixed-shape
+// tree in LDS, so the result does not depend on scheduling.
+#pragma once
+
+#include "common.hpp"
+
+namespace sicp {
+
+struct GradArgs {
+    const PairDesc* pairs;
+    const float4* src4;
+    const float4* ref4;
+    const int32_t* sched;
+    const Pose* pose;
+    const int64_t* step;
+    const uint64_t* partial;
+    int32_t* match;       // K*m per pair, pair-relative reference indices
+    double* gbar;         // 6 per particle
+    int32_t K, m, rows, pad_;
+};
+
+__global__ __launch_bounds__(kGradThreads) void grad_kernel(GradArgs a)
+{
+    const int64_t pk = blockIdx.x;
+    const int64_t p = pk / a.K;
+    const int64_t k = pk - p * a.K;
+    const PairDesc pd = a.pairs[p];
+    const int64_t nq = (int64_t)a.K * a.m;
+    const int64_t row = a.step[p] % a.rows;
+    const Pose* __restrict__ P = a.pose + pk;
+
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < a.m; i += kGradThreads) {
+        const int64_t qi = k * a.m + i;
+        uint64_t key = ~0ull;
+        const uint64_t* __restrict__ kp = a.partial + pd.part_off + qi;
+        for (int c = 0; c < pd.chunks; ++c) key = min(key, kp[(int64_t)c * nq]);
+        const int32_t j = (int32_t)(uint32_t)(key & 0xffffffffull);
+        a.match[p * nq + qi] = j;
+        const float4 s = a.src4[pd.src_off + a.sched[pd.sched_off + row * a.m + i]];
+        const float4 r = a.ref4[pd.ref_off + j];
+        double q[3];
+        transform_f64(P->R, P->u, s.x, s.y, s.z, q);
+        {
+#pragma clang fp contract(off)
+            const double e0 = q[0] - (double)r.x, e1 = q[1] - (double)r.y, e2 = q[2] - (double)r.z;
+            acc[0] += e0;
+            acc[1] += e1;
+            acc[2] += e2;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double* D = P->dR + 9 * d;
+                const double v0 = (D[0] * s.x + D[1] * s.y) + D[2] * s.z;
+                const double v1 = (D[3] * s.x + D[4] * s.y) + D[5] * s.z;
+                const double v2 = (D[6] * s.x + D[7] * s.y) + D[8] * s.z;
+                acc[3 + d] += (e0 * v0 + e1 * v1) + e2 * v2;
+            }
+        }
+    }
+
+    __shared__ double red[6][kGradThreads];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) red[d][threadIdx.x] = acc[d];
+    __syncthreads();
+    for (int w = kGradThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) a.gbar[pk * 6 + threadIdx.x] = red[threadIdx.x][0] / (double)a.m;
+}
+
+}  // namespace sicp

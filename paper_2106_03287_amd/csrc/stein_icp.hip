@@ -1,0 +1,875 @@
+// Host side of the Stein-ICP library: validation, device layout, tiling,
+// hipGraph capture and the C ABI declared in include/stein_icp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "stein_icp.h"
+
+#include "common.hpp"
+#include "grad.hpp"
+#include "nn.hpp"
+#include "prep.hpp"
+#include "svgd.hpp"
+
+using namespace sicp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(STEIN_ICP_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+inline int64_t ceil_div(int64_t v, int64_t a) { return (v + a - 1) / a; }
+inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// ------------------------------------------------------------------ host RNG
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014).
+struct SplitMix64 {
+    uint64_t s;
+    uint64_t next()
+    {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return (double)(next() >> 11) * 0x1.0p-53; }  // [0, 1)
+};
+
+void make_schedule(uint64_t seed, int64_t n, int32_t m, int32_t rows, int32_t* out)
+{
+    SplitMix64 g{seed ^ 0x5DEECE66Dull};
+    std::vector<uint8_t> used((size_t)n, 0);
+    for (int32_t r = 0; r < rows; ++r) {
+        int32_t* row = out + (int64_t)r * m;
+        int32_t c = 0;
+        // Floyd's algorithm: m distinct values from [0, n)
+        for (int64_t j = n - m; j < n; ++j) {
+            const int64_t t = (int64_t)(g.next() % (uint64_t)(j + 1));
+            const int64_t v = used[(size_t)t] ? j : t;
+            used[(size_t)v] = 1;
+            row[c++] = (int32_t)v;
+        }
+        for (int32_t i = 0; i < m; ++i) used[(size_t)row[i]] = 0;
+    }
+}
+
+void make_init(uint64_t seed, int32_t K, double ht, double hr, const double* centre, double* out)
+{
+    SplitMix64 g{seed ^ 0xA0761D6478BD642Full};
+    for (int32_t k = 0; k < K; ++k)
+        for (int d = 0; d < 6; ++d) {
+            const double c = centre ? centre[d] : 0.0;
+            const double h = d < 3 ? ht : hr;
+            out[6 * k + d] = c + (2.0 * g.uniform() - 1.0) * h;
+        }
+}
+
+// ------------------------------------------------------------------ tiling
+struct Tiling {
+    int q = 2;                   // queries per lane
+    std::vector<int32_t> chunk;  // per pair, references per chunk
+};
+
+// Default shape: enough workgroups to give every SIMD several waves, with at
+// least 256 references (16 tiles) per wave so the fixed per-wave work (query
+// transform, index recovery, merge) stays small.
+Tiling default_tiling(const std::vector<PairDesc>& pd, int64_t nq)
+{
+    Tiling t;
+    t.q = nq >= 65536 ? 4 : (nq >= 8192 ? 2 : 1);
+    const int64_t qb = ceil_div(nq, (int64_t)kWave * t.q);
+    const int64_t target_wg = 4096;  // x4 waves = 16k waves over 1024 SIMDs
+    const int64_t per_pair = std::max<int64_t>(1, ceil_div(target_wg, (int64_t)pd.size() * qb));
+    for (const auto& p : pd) {
+        const int64_t max_chunks = std::max<int64_t>(1, p.n_ref_pad / (4 * 256));
+        const int64_t c = std::min(per_pair, max_chunks);
+        t.chunk.push_back((int32_t)round_up(ceil_div(p.n_ref_pad, c), 4 * kTile));
+    }
+    return t;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct stein_icp_ctx {
+    stein_icp_config cfg{};
+    int device = 0;
+    int32_t P = 0, K = 0, m = 0, rows = 0;
+    int64_t nq = 0;  // K * m per pair
+    std::vector<PairDesc> pairs;
+    Tiling tiling;
+    std::vector<WorkItem> work;
+    double tuned_ms = 0.0;
+
+    char* arena = nullptr;
+    PairDesc* d_pairs = nullptr;
+    float4* src4 = nullptr;
+    float4* ref4 = nullptr;
+    int32_t* sched = nullptr;
+    double *theta = nullptr, *mom = nullptr, *vel = nullptr, *G = nullptr, *gbar = nullptr, *phi = nullptr;
+    double* h = nullptr;
+    int64_t* step = nullptr;
+    Pose* pose = nullptr;
+    int32_t* match = nullptr;
+    double* dscr = nullptr;
+    int* flag = nullptr;
+
+    WorkItem* d_work = nullptr;  // separate allocations: resized by the tuner
+    uint64_t* partial = nullptr;
+
+    hipStream_t cap_stream = nullptr;
+    std::map<int, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+SvgdParams svgd_params(const stein_icp_config& c)
+{
+    SvgdParams p{};
+    p.lr = c.lr;
+    p.beta1 = c.beta1;
+    p.beta2 = c.beta2;
+    p.eps = c.eps;
+    p.h_fixed_t = c.fixed_h_trans;
+    p.h_fixed_r = c.fixed_h_rot;
+    for (int i = 0; i < 6; ++i) p.prior_mu[i] = c.prior_mu[i];
+    for (int i = 0; i < 3; ++i) {
+        p.prior_var[i] = c.prior_var_trans[i];
+        p.prior_kappa[i] = c.prior_kappa_rot[i];
+    }
+    p.optimizer = c.optimizer;
+    p.bandwidth = c.bandwidth_mode;
+    p.prior = c.prior_mode;
+    return p;
+}
+
+int validate_config(const stein_icp_config* c)
+{
+    if (!c) return fail(STEIN_ICP_E_INVALID, "cfg is NULL");
+    if (c->struct_size != sizeof(stein_icp_config))
+        return fail(STEIN_ICP_E_INVALID, "cfg->struct_size does not match this library's stein_icp_config");
+    if (c->num_particles < 1 || c->num_particles > kMaxK)
+        return fail(STEIN_ICP_E_INVALID, "num_particles must be in [1, 1024]");
+    if (c->batch_size < 1) return fail(STEIN_ICP_E_INVALID, "batch_size must be >= 1");
+    if (c->schedule_rows < 1) return fail(STEIN_ICP_E_INVALID, "schedule_rows must be >= 1");
+    if ((int64_t)c->schedule_rows * c->batch_size > (int64_t)1 << 31)
+        return fail(STEIN_ICP_E_INVALID, "schedule_rows * batch_size too large");
+    if (!finite_pos(c->lr)) return fail(STEIN_ICP_E_INVALID, "lr must be finite and > 0");
+    if (!(c->beta1 >= 0.0 && c->beta1 < 1.0) || !(c->beta2 >= 0.0 && c->beta2 < 1.0))
+        return fail(STEIN_ICP_E_INVALID, "beta1 and beta2 must be in [0, 1)");
+    if (!finite_pos(c->eps)) return fail(STEIN_ICP_E_INVALID, "eps must be finite and > 0");
+    if (!(std::isfinite(c->init_half_trans) && c->init_half_trans >= 0.0) ||
+        !(std::isfinite(c->init_half_rot) && c->init_half_rot >= 0.0))
+        return fail(STEIN_ICP_E_INVALID, "init half widths must be finite and >= 0");
+    for (int i = 0; i < 6; ++i)
+        if (!std::isfinite(c->init_centre[i])) return fail(STEIN_ICP_E_INVALID, "init_centre must be finite");
+    if (c->nn_mode != STEIN_ICP_NN_FP32 && c->nn_mode != STEIN_ICP_NN_BF16_RERANK)
+        return fail(STEIN_ICP_E_INVALID, "unknown nn_mode");
+    if (c->nn_mode == STEIN_ICP_NN_BF16_RERANK)
+        return fail(STEIN_ICP_E_INVALID, "nn_mode BF16_RERANK is not available in this build");
+    if (c->optimizer != STEIN_ICP_OPT_ADAM && c->optimizer != STEIN_ICP_OPT_SGD)
+        return fail(STEIN_ICP_E_INVALID, "unknown optimizer");
+    if (c->bandwidth_mode != STEIN_ICP_BW_MEDIAN && c->bandwidth_mode != STEIN_ICP_BW_FIXED)
+        return fail(STEIN_ICP_E_INVALID, "unknown bandwidth_mode");
+    if (c->bandwidth_mode == STEIN_ICP_BW_FIXED && (!finite_pos(c->fixed_h_trans) || !finite_pos(c->fixed_h_rot)))
+        return fail(STEIN_ICP_E_INVALID, "fixed bandwidths must be finite and > 0");
+    if (c->prior_mode != STEIN_ICP_PRIOR_UNIFORM && c->prior_mode != STEIN_ICP_PRIOR_GAUSS_VONMISES)
+        return fail(STEIN_ICP_E_INVALID, "unknown prior_mode");
+    if (c->prior_mode == STEIN_ICP_PRIOR_GAUSS_VONMISES) {
+        for (int i = 0; i < 6; ++i)
+            if (!std::isfinite(c->prior_mu[i])) return fail(STEIN_ICP_E_INVALID, "prior_mu must be finite");
+        for (int i = 0; i < 3; ++i) {
+            if (!finite_pos(c->prior_var_trans[i]))
+                return fail(STEIN_ICP_E_INVALID, "prior_var_trans must be finite and > 0");
+            if (!(std::isfinite(c->prior_kappa_rot[i]) && c->prior_kappa_rot[i] >= 0.0))
+                return fail(STEIN_ICP_E_INVALID, "prior_kappa_rot must be finite and >= 0");
+        }
+    }
+    if (c->n_scale < 0) return fail(STEIN_ICP_E_INVALID, "n_scale must be >= 0");
+    if (c->use_graph != 0 && c->use_graph != 1) return fail(STEIN_ICP_E_INVALID, "use_graph must be 0 or 1");
+    if (c->autotune != 0 && c->autotune != 1) return fail(STEIN_ICP_E_INVALID, "autotune must be 0 or 1");
+    return STEIN_ICP_OK;
+}
+
+constexpr int64_t kMaxRef = ((int64_t)1 << 31) - 64;
+
+dim3 grid1d(int64_t n, int threads) { return dim3((unsigned)ceil_div(std::max<int64_t>(n, 1), threads)); }
+
+// Launch the NN kernel for the context's queries (FROM_POSE) or direct queries.
+template <bool FROM_POSE>
+hipError_t launch_nn(int q, unsigned nwork, const NNArgs& a, hipStream_t s)
+{
+    if (nwork == 0) return hipSuccess;
+    switch (q) {
+    case 1: hipLaunchKernelGGL((nn_fp32_kernel<1, FROM_POSE>), dim3(nwork), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((nn_fp32_kernel<2, FROM_POSE>), dim3(nwork), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((nn_fp32_kernel<4, FROM_POSE>), dim3(nwork), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+void build_work(stein_icp_ctx* c)
+{
+    c->work.clear();
+    int64_t part = 0;
+    for (int32_t p = 0; p < c->P; ++p) {
+        PairDesc& pd = c->pairs[p];
+        pd.chunk = c->tiling.chunk[p];
+        pd.chunks = (int32_t)ceil_div(pd.n_ref_pad, pd.chunk);
+        pd.qblocks = (int32_t)ceil_div(c->nq, (int64_t)kWave * c->tiling.q);
+        pd.part_off = part;
+        part += (int64_t)pd.chunks * c->nq;
+    }
+    // chunk-major order inside a pair so neighbouring workgroups (which the
+    // dispatcher spreads round-robin over the eight XCDs) read different
+    // chunks of the same queries; every reference array here fits each
+    // XCD's L2, so locality across XCDs is not the limiter.
+    for (int32_t p = 0; p < c->P; ++p) {
+        const PairDesc& pd = c->pairs[p];
+        for (int32_t b = 0; b < pd.qblocks; ++b)
+            for (int32_t ch = 0; ch < pd.chunks; ++ch) c->work.push_back(WorkItem{p, b, ch, 0});
+    }
+}
+
+int64_t partial_elems(const stein_icp_ctx* c)
+{
+    int64_t n = 0;
+    for (const auto& pd : c->pairs) n += (int64_t)pd.chunks * c->nq;
+    return n;
+}
+
+int upload_tiling(stein_icp_ctx* c, hipStream_t s)
+{
+    build_work(c);
+    if (c->d_work) HIP_TRY(hipFree(c->d_work));
+    if (c->partial) HIP_TRY(hipFree(c->partial));
+    c->d_work = nullptr;
+    c->partial = nullptr;
+    if (hipMalloc(&c->d_work, sizeof(WorkItem) * std::max<size_t>(c->work.size(), 1)) != hipSuccess ||
+        hipMalloc(&c->partial, sizeof(uint64_t) * std::max<int64_t>(partial_elems(c), 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(STEIN_ICP_E_NOMEM, "device allocation of the NN work table failed");
+    }
+    HIP_TRY(hipMemcpyAsync(c->d_pairs, c->pairs.data(), sizeof(PairDesc) * c->P, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c->d_work, c->work.data(), sizeof(WorkItem) * c->work.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+    return STEIN_ICP_OK;
+}
+
+NNArgs nn_args(const stein_icp_ctx* c)
+{
+    NNArgs a{};
+    a.work = c->d_work;
+    a.pairs = c->d_pairs;
+    a.src4 = c->src4;
+    a.ref4 = c->ref4;
+    a.sched = c->sched;
+    a.pose = c->pose;
+    a.step = c->step;
+    a.queries = nullptr;
+    a.partial = c->partial;
+    a.K = c->K;
+    a.m = c->m;
+    a.rows = c->rows;
+    return a;
+}
+
+// Stage 0: nearest neighbours, 1: gradients, 2: Stein direction and update.
+hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
+{
+    if (stage == 0) return launch_nn<true>(c->tiling.q, (unsigned)c->work.size(), nn_args(c), s);
+    if (stage == 1) {
+    GradArgs g{};
+    g.pairs = c->d_pairs;
+    g.src4 = c->src4;
+    g.ref4 = c->ref4;
+    g.sched = c->sched;
+    g.pose = c->pose;
+    g.step = c->step;
+    g.partial = c->partial;
+    g.match = c->match;
+    g.gbar = c->gbar;
+    g.K = c->K;
+    g.m = c->m;
+    g.rows = c->rows;
+    hipLaunchKernelGGL(grad_kernel, dim3((unsigned)((int64_t)c->P * c->K)), dim3(kGradThreads), 0, s, g);
+    return hipGetLastError();
+    }
+    SvgdArgs v{};
+    v.pairs = c->d_pairs;
+    v.theta = c->theta;
+    v.mom = c->mom;
+    v.vel = c->vel;
+    v.step = c->step;
+    v.gbar = c->gbar;
+    v.G = c->G;
+    v.phi = c->phi;
+    v.h = c->h;
+    v.dscr = c->dscr;
+    v.pose = c->pose;
+    v.K = c->K;
+    v.prm = svgd_params(c->cfg);
+    hipLaunchKernelGGL(svgd_update_kernel, dim3((unsigned)c->P), dim3(kSvgdThreads), 0, s, v);
+    return hipGetLastError();
+}
+
+hipError_t enqueue_iteration(const stein_icp_ctx* c, hipStream_t s)
+{
+    for (int st = 0; st < 3; ++st) {
+        const hipError_t e = enqueue_stage(c, st, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int get_graph(stein_icp_ctx* c, int len, hipGraphExec_t* out)
+{
+    auto it = c->graphs.find(len);
+    if (it != c->graphs.end()) {
+        *out = it->second;
+        return STEIN_ICP_OK;
+    }
+    if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < len && e == hipSuccess; ++i) e = enqueue_iteration(c, c->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(STEIN_ICP_E_DEVICE, std::string("graph capture failed: ") +
+                                            hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(STEIN_ICP_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    c->graphs[len] = ex;
+    *out = ex;
+    return STEIN_ICP_OK;
+}
+
+constexpr int kGraphIters = 25;
+
+int run_iters(stein_icp_ctx* c, int32_t n, hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &st));
+    if (!c->cfg.use_graph || st != hipStreamCaptureStatusNone) {
+        for (int32_t i = 0; i < n; ++i) HIP_TRY(enqueue_iteration(c, s));
+        return STEIN_ICP_OK;
+    }
+    int32_t left = n;
+    while (left > 0) {
+        const int len = std::min<int32_t>(left, kGraphIters);
+        hipGraphExec_t ex;
+        int rc = get_graph(c, len, &ex);
+        if (rc) return rc;
+        HIP_TRY(hipGraphLaunch(ex, s));
+        left -= len;
+    }
+    return STEIN_ICP_OK;
+}
+
+// Autotuner: time candidate tile shapes on the context's own data with the
+// real kernel, keep the fastest. Each candidate changes only the NN work
+// decomposition, never the arithmetic, so results are identical across
+// shapes.
+int autotune(stein_icp_ctx* c, hipStream_t s)
+{
+    struct Cand {
+        int q;
+        int64_t per_wave;
+    };
+    std::vector<Cand> cands;
+    for (int q : {1, 2, 4})
+        for (int64_t pw : {256, 512, 1024, 2048, 4096}) cands.push_back({q, pw});
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best = 1e30;
+    Tiling best_t = c->tiling;
+    for (const Cand& cd : cands) {
+        Tiling t;
+        t.q = cd.q;
+        for (const auto& pd : c->pairs) {
+            const int64_t chunks = std::max<int64_t>(1, ceil_div(pd.n_ref_pad, 4 * cd.per_wave));
+            t.chunk.push_back((int32_t)round_up(ceil_div(pd.n_ref_pad, chunks), 4 * kTile));
+        }
+        c->tiling = t;
+        int rc = upload_tiling(c, s);
+        if (rc) return rc;
+        const NNArgs a = nn_args(c);
+        HIP_TRY(launch_nn<true>(t.q, (unsigned)c->work.size(), a, s));  // warm-up
+        const int reps = 5;
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) HIP_TRY(launch_nn<true>(t.q, (unsigned)c->work.size(), a, s));
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms / reps < best) {
+            best = ms / reps;
+            best_t = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->tiling = best_t;
+    c->tuned_ms = best;
+    return upload_tiling(c, s);
+}
+
+void free_ctx(stein_icp_ctx* c)
+{
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->arena) (void)hipFree(c->arena);
+    if (c->d_work) (void)hipFree(c->d_work);
+    if (c->partial) (void)hipFree(c->partial);
+    delete c;
+}
+
+int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const float* const* src,
+              const int64_t* n_src, const float* const* ref, const int64_t* n_ref, const double* init,
+              const int32_t* const* sched, hipStream_t s)
+{
+    if (!out) return fail(STEIN_ICP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc = validate_config(cfg);
+    if (rc) return rc;
+    if (P < 1) return fail(STEIN_ICP_E_INVALID, "n_pairs must be >= 1");
+    if (!src || !n_src || !ref || !n_ref) return fail(STEIN_ICP_E_INVALID, "cloud arrays are NULL");
+    const int32_t K = cfg->num_particles, m = cfg->batch_size, rows = cfg->schedule_rows;
+    for (int32_t p = 0; p < P; ++p) {
+        if (!src[p] || !ref[p]) return fail(STEIN_ICP_E_INVALID, "a cloud pointer is NULL");
+        if (n_src[p] < 1 || n_ref[p] < 1) return fail(STEIN_ICP_E_INVALID, "clouds must hold >= 1 point");
+        if (n_ref[p] > kMaxRef || n_src[p] > kMaxRef)
+            return fail(STEIN_ICP_E_INVALID, "clouds must hold fewer than 2^31 - 64 points");
+        if (m > n_src[p]) return fail(STEIN_ICP_E_INVALID, "batch_size exceeds a source cloud size");
+        if (sched && !sched[p]) return fail(STEIN_ICP_E_INVALID, "a schedule pointer is NULL");
+    }
+    const int64_t nq = (int64_t)K * m;
+    if (nq > ((int64_t)1 << 31)) return fail(STEIN_ICP_E_INVALID, "K * batch_size too large");
+
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    auto* c = new stein_icp_ctx();
+    c->device = device;
+    c->cfg = *cfg;
+    c->P = P;
+    c->K = K;
+    c->m = m;
+    c->rows = rows;
+    c->nq = nq;
+
+    // layout
+    int64_t so = 0, ro = 0;
+    for (int32_t p = 0; p < P; ++p) {
+        PairDesc pd{};
+        pd.src_off = so;
+        pd.ref_off = ro;
+        pd.n_src = n_src[p];
+        pd.n_ref = n_ref[p];
+        pd.n_ref_pad = round_up(n_ref[p], kTile);
+        pd.sched_off = (int64_t)p * rows * m;
+        pd.n_scale = cfg->n_scale > 0 ? cfg->n_scale : n_src[p];
+        so += pd.n_src;
+        ro += pd.n_ref_pad;
+        c->pairs.push_back(pd);
+    }
+    c->tiling = default_tiling(c->pairs, nq);
+    const int64_t PK6 = (int64_t)P * K * 6;
+    const int64_t npairs2 = K >= 2 ? (int64_t)K * (K - 1) : 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = (size_t)round_up((int64_t)(off + bytes), 256);
+        return o;
+    };
+    const size_t o_pairs = take(sizeof(PairDesc) * P);
+    const size_t o_src = take(sizeof(float4) * so);
+    const size_t o_ref = take(sizeof(float4) * ro);
+    const size_t o_sched = take(sizeof(int32_t) * (size_t)P * rows * m);
+    const size_t o_theta = take(8 * PK6), o_mom = take(8 * PK6), o_vel = take(8 * PK6);
+    const size_t o_G = take(8 * PK6), o_gbar = take(8 * PK6), o_phi = take(8 * PK6);
+    const size_t o_h = take(8 * 2 * (size_t)P);
+    const size_t o_step = take(8 * (size_t)P);
+    const size_t o_pose = take(sizeof(Pose) * (size_t)P * K);
+    const size_t o_match = take(4 * (size_t)P * nq);
+    const size_t o_dscr = take(8 * (size_t)P * npairs2);
+    const size_t o_flag = take(64);
+    if (hipMalloc(&c->arena, off) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return fail(STEIN_ICP_E_NOMEM, "device allocation of " + std::to_string(off) + " bytes failed");
+    }
+    c->d_pairs = (PairDesc*)(c->arena + o_pairs);
+    c->src4 = (float4*)(c->arena + o_src);
+    c->ref4 = (float4*)(c->arena + o_ref);
+    c->sched = (int32_t*)(c->arena + o_sched);
+    c->theta = (double*)(c->arena + o_theta);
+    c->mom = (double*)(c->arena + o_mom);
+    c->vel = (double*)(c->arena + o_vel);
+    c->G = (double*)(c->arena + o_G);
+    c->gbar = (double*)(c->arena + o_gbar);
+    c->phi = (double*)(c->arena + o_phi);
+    c->h = (double*)(c->arena + o_h);
+    c->step = (int64_t*)(c->arena + o_step);
+    c->pose = (Pose*)(c->arena + o_pose);
+    c->match = (int32_t*)(c->arena + o_match);
+    c->dscr = (double*)(c->arena + o_dscr);
+    c->flag = (int*)(c->arena + o_flag);
+
+    auto bail = [&](int code) {
+        free_ctx(c);
+        return code;
+    };
+    if (hipMemsetAsync(c->arena, 0, off, s) != hipSuccess) return bail(fail(STEIN_ICP_E_DEVICE, "hipMemsetAsync failed"));
+
+    std::vector<int32_t> hsched;
+    std::vector<double> hinit;
+    for (int32_t p = 0; p < P; ++p) {
+        const PairDesc& pd = c->pairs[p];
+        hipLaunchKernelGGL(pack_points_kernel, grid1d(pd.n_src, 256), dim3(256), 0, s, src[p], pd.n_src, pd.n_src,
+                           c->src4 + pd.src_off, c->flag);
+        hipLaunchKernelGGL(pack_points_kernel, grid1d(pd.n_ref_pad, 256), dim3(256), 0, s, ref[p], pd.n_ref,
+                           pd.n_ref_pad, c->ref4 + pd.ref_off, c->flag);
+        const int64_t ns = (int64_t)rows * m;
+        if (sched) {
+            hipLaunchKernelGGL(copy_schedule_kernel, grid1d(ns, 256), dim3(256), 0, s, sched[p], ns, pd.n_src,
+                               c->sched + pd.sched_off, c->flag);
+        } else {
+            const size_t o = hsched.size();
+            hsched.resize(o + (size_t)ns);
+            make_schedule(cfg->seed + (uint64_t)p, pd.n_src, m, rows, hsched.data() + o);
+        }
+    }
+    if (!sched && hipMemcpyAsync(c->sched, hsched.data(), 4 * hsched.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        return bail(fail(STEIN_ICP_E_DEVICE, "schedule upload failed"));
+    if (init) {
+        hipLaunchKernelGGL(copy_finite_kernel, grid1d(PK6, 256), dim3(256), 0, s, init, PK6, c->theta, c->flag);
+    } else {
+        hinit.resize((size_t)PK6);
+        for (int32_t p = 0; p < P; ++p)
+            make_init(cfg->seed + (uint64_t)p, K, cfg->init_half_trans, cfg->init_half_rot, cfg->init_centre,
+                      hinit.data() + (size_t)p * K * 6);
+        if (hipMemcpyAsync(c->theta, hinit.data(), 8 * hinit.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+            return bail(fail(STEIN_ICP_E_DEVICE, "particle upload failed"));
+    }
+    hipLaunchKernelGGL(pose_kernel, grid1d((int64_t)P * K, 256), dim3(256), 0, s, c->theta, c->pose, (int64_t)P * K);
+    if (hipGetLastError() != hipSuccess) return bail(fail(STEIN_ICP_E_DEVICE, "init kernel launch failed"));
+    int flag = 0;
+    if (hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return bail(fail(STEIN_ICP_E_DEVICE, "init synchronisation failed"));
+    if (flag & 1) return bail(fail(STEIN_ICP_E_INVALID, "a cloud holds a non-finite coordinate or one above 1e9"));
+    if (flag & 2) return bail(fail(STEIN_ICP_E_INVALID, "a schedule index lies outside [0, n_src)"));
+    if (flag & 4) return bail(fail(STEIN_ICP_E_INVALID, "an initial particle is non-finite"));
+    rc = upload_tiling(c, s);
+    if (rc) return bail(rc);
+    if (cfg->autotune) {
+        rc = autotune(c, s);
+        if (rc) return bail(rc);
+        // the tuner ran real iterations' NN stage only; the state is untouched
+    }
+    *out = c;
+    g_err.clear();
+    return STEIN_ICP_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+void stein_icp_default_config(stein_icp_config* c)
+{
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->struct_size = sizeof(stein_icp_config);
+    c->num_particles = 100;
+    c->batch_size = 300;
+    c->schedule_rows = 1;
+    c->lr = 0.01;
+    c->beta1 = 0.9;
+    c->beta2 = 0.999;
+    c->eps = 1e-8;
+    c->init_half_trans = 0.2;
+    c->init_half_rot = M_PI / 4;
+    c->nn_mode = STEIN_ICP_NN_FP32;
+    c->optimizer = STEIN_ICP_OPT_ADAM;
+    c->bandwidth_mode = STEIN_ICP_BW_MEDIAN;
+    c->prior_mode = STEIN_ICP_PRIOR_UNIFORM;
+    c->fixed_h_trans = 1.0;
+    c->fixed_h_rot = 1.0;
+    for (int i = 0; i < 3; ++i) {
+        c->prior_var_trans[i] = 1.0;
+        c->prior_kappa_rot[i] = 0.0;
+    }
+    c->use_graph = 1;
+}
+
+const char* stein_icp_last_error(void) { return g_err.c_str(); }
+
+int stein_icp_init(stein_icp_ctx** out, const stein_icp_config* cfg, const float* src_xyz, int64_t n_src,
+                   const float* ref_xyz, int64_t n_ref, const double* init_particles, const int32_t* schedule,
+                   void* hip_stream)
+{
+    const float* s[1] = {src_xyz};
+    const float* r[1] = {ref_xyz};
+    const int32_t* sc[1] = {schedule};
+    return init_impl(out, cfg, 1, s, &n_src, r, &n_ref, init_particles, schedule ? sc : nullptr,
+                     (hipStream_t)hip_stream);
+}
+
+int stein_icp_batch_init(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t n_pairs,
+                         const float* const* src_xyz, const int64_t* n_src, const float* const* ref_xyz,
+                         const int64_t* n_ref, const double* init_particles, const int32_t* const* schedules,
+                         void* hip_stream)
+{
+    return init_impl(out, cfg, n_pairs, src_xyz, n_src, ref_xyz, n_ref, init_particles, schedules,
+                     (hipStream_t)hip_stream);
+}
+
+int stein_icp_step(stein_icp_ctx* ctx, int32_t n_iters, void* hip_stream)
+{
+    if (!ctx) return fail(STEIN_ICP_E_INVALID, "ctx is NULL");
+    if (n_iters < 0) return fail(STEIN_ICP_E_INVALID, "n_iters must be >= 0");
+    return run_iters(ctx, n_iters, (hipStream_t)hip_stream);
+}
+
+int stein_icp_particles(const stein_icp_ctx* ctx, double* out, void* hip_stream)
+{
+    if (!ctx || !out) return fail(STEIN_ICP_E_INVALID, "ctx or out is NULL");
+    HIP_TRY(hipMemcpyAsync(out, ctx->theta, 8 * (size_t)ctx->P * ctx->K * 6, hipMemcpyDeviceToDevice,
+                           (hipStream_t)hip_stream));
+    return STEIN_ICP_OK;
+}
+
+int stein_icp_get_state(const stein_icp_ctx* ctx, double* theta, double* mom, double* vel, int64_t* t,
+                        void* hip_stream)
+{
+    if (!ctx) return fail(STEIN_ICP_E_INVALID, "ctx is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t bytes = 8 * (size_t)ctx->P * ctx->K * 6;
+    if (theta) HIP_TRY(hipMemcpyAsync(theta, ctx->theta, bytes, hipMemcpyDeviceToDevice, s));
+    if (mom) HIP_TRY(hipMemcpyAsync(mom, ctx->mom, bytes, hipMemcpyDeviceToDevice, s));
+    if (vel) HIP_TRY(hipMemcpyAsync(vel, ctx->vel, bytes, hipMemcpyDeviceToDevice, s));
+    int64_t tt = 0;
+    HIP_TRY(hipMemcpyAsync(&tt, ctx->step, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (t) *t = tt;
+    return STEIN_ICP_OK;
+}
+
+int stein_icp_set_state(stein_icp_ctx* ctx, const double* theta, const double* mom, const double* vel, int64_t t,
+                        void* hip_stream)
+{
+    if (!ctx || !theta) return fail(STEIN_ICP_E_INVALID, "ctx or theta is NULL");
+    if (t < 0) return fail(STEIN_ICP_E_INVALID, "t must be >= 0");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t n = (int64_t)ctx->P * ctx->K * 6;
+    HIP_TRY(hipMemcpyAsync(ctx->theta, theta, 8 * n, hipMemcpyDeviceToDevice, s));
+    if (mom) HIP_TRY(hipMemcpyAsync(ctx->mom, mom, 8 * n, hipMemcpyDeviceToDevice, s));
+    else hipLaunchKernelGGL(fill_f64_kernel, grid1d(n, 256), dim3(256), 0, s, ctx->mom, n, 0.0);
+    if (vel) HIP_TRY(hipMemcpyAsync(ctx->vel, vel, 8 * n, hipMemcpyDeviceToDevice, s));
+    else hipLaunchKernelGGL(fill_f64_kernel, grid1d(n, 256), dim3(256), 0, s, ctx->vel, n, 0.0);
+    hipLaunchKernelGGL(fill_i64_kernel, grid1d(ctx->P, 256), dim3(256), 0, s, ctx->step, (int64_t)ctx->P, t);
+    hipLaunchKernelGGL(pose_kernel, grid1d((int64_t)ctx->P * ctx->K, 256), dim3(256), 0, s, ctx->theta, ctx->pose,
+                       (int64_t)ctx->P * ctx->K);
+    HIP_TRY(hipGetLastError());
+    return STEIN_ICP_OK;
+}
+
+int stein_icp_get_diagnostics(const stein_icp_ctx* ctx, double* gbar, double* phi, double* h, int32_t* match,
+                              void* hip_stream)
+{
+    if (!ctx) return fail(STEIN_ICP_E_INVALID, "ctx is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t b6 = 8 * (size_t)ctx->P * ctx->K * 6;
+    if (gbar) HIP_TRY(hipMemcpyAsync(gbar, ctx->gbar, b6, hipMemcpyDeviceToDevice, s));
+    if (phi) HIP_TRY(hipMemcpyAsync(phi, ctx->phi, b6, hipMemcpyDeviceToDevice, s));
+    if (h) HIP_TRY(hipMemcpyAsync(h, ctx->h, 16 * (size_t)ctx->P, hipMemcpyDeviceToDevice, s));
+    if (match) HIP_TRY(hipMemcpyAsync(match, ctx->match, 4 * (size_t)ctx->P * ctx->nq, hipMemcpyDeviceToDevice, s));
+    return STEIN_ICP_OK;
+}
+
+int stein_icp_shape(const stein_icp_ctx* ctx, int32_t* n_pairs, int32_t* K, int32_t* m)
+{
+    if (!ctx) return fail(STEIN_ICP_E_INVALID, "ctx is NULL");
+    if (n_pairs) *n_pairs = ctx->P;
+    if (K) *K = ctx->K;
+    if (m) *m = ctx->m;
+    return STEIN_ICP_OK;
+}
+
+int stein_icp_nn_tiling(const stein_icp_ctx* ctx, int32_t* qpl, int32_t* chunk, int32_t* chunks, double* tuned_ms)
+{
+    if (!ctx) return fail(STEIN_ICP_E_INVALID, "ctx is NULL");
+    if (qpl) *qpl = ctx->tiling.q;
+    if (chunk) *chunk = ctx->pairs[0].chunk;
+    if (chunks) *chunks = ctx->pairs[0].chunks;
+    if (tuned_ms) *tuned_ms = ctx->tuned_ms;
+    return STEIN_ICP_OK;
+}
+
+int stein_icp_stage_times(stein_icp_ctx* ctx, int32_t n_iters, double* ms_out, void* hip_stream)
+{
+    if (!ctx || !ms_out) return fail(STEIN_ICP_E_INVALID, "ctx or ms_out is NULL");
+    if (n_iters < 1) return fail(STEIN_ICP_E_INVALID, "n_iters must be >= 1");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &st));
+    if (st != hipStreamCaptureStatusNone) return fail(STEIN_ICP_E_STATE, "stream is capturing");
+    std::vector<hipEvent_t> ev((size_t)n_iters * 4, nullptr);
+    int rc = STEIN_ICP_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, "hipEventCreate failed");
+    for (int32_t i = 0; i < n_iters && rc == STEIN_ICP_OK; ++i) {
+        hipEvent_t* e = ev.data() + 4 * (size_t)i;
+        hipError_t err = hipEventRecord(e[0], s);
+        if (err == hipSuccess) err = enqueue_stage(ctx, 0, s);
+        if (err == hipSuccess) err = hipEventRecord(e[1], s);
+        if (err == hipSuccess) err = enqueue_stage(ctx, 1, s);
+        if (err == hipSuccess) err = hipEventRecord(e[2], s);
+        if (err == hipSuccess) err = enqueue_stage(ctx, 2, s);
+        if (err == hipSuccess) err = hipEventRecord(e[3], s);
+        if (err != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, std::string("profiled step: ") + hipGetErrorString(err));
+    }
+    if (rc == STEIN_ICP_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, "sync failed");
+    double t[3] = {0, 0, 0};
+    for (int32_t i = 0; i < n_iters && rc == STEIN_ICP_OK; ++i)
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[4 * (size_t)i + k], ev[4 * (size_t)i + k + 1]) != hipSuccess)
+                rc = fail(STEIN_ICP_E_DEVICE, "hipEventElapsedTime failed");
+            t[k] += ms;
+        }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc == STEIN_ICP_OK)
+        for (int k = 0; k < 3; ++k) ms_out[k] = t[k];
+    return rc;
+}
+
+void stein_icp_destroy(stein_icp_ctx* ctx) { free_ctx(ctx); }
+
+int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n_ref, int32_t mode, int32_t* idx,
+                 float* d2, void* hip_stream)
+{
+    if (nq < 0 || n_ref < 1) return fail(STEIN_ICP_E_INVALID, "need nq >= 0 and n_ref >= 1");
+    if (nq > kMaxRef || n_ref > kMaxRef) return fail(STEIN_ICP_E_INVALID, "sizes must be below 2^31 - 64");
+    if (mode != STEIN_ICP_NN_FP32) return fail(STEIN_ICP_E_INVALID, "unknown or unavailable nn mode");
+    if (nq == 0) return STEIN_ICP_OK;
+    if (!q_xyz || !ref_xyz || !idx) return fail(STEIN_ICP_E_INVALID, "a pointer is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    PairDesc pd{};
+    pd.src_off = 0;
+    pd.n_src = nq;
+    pd.n_ref = n_ref;
+    pd.n_ref_pad = round_up(n_ref, kTile);
+    std::vector<PairDesc> v{pd};
+    Tiling t = default_tiling(v, nq);
+    pd.chunk = t.chunk[0];
+    pd.chunks = (int32_t)ceil_div(pd.n_ref_pad, pd.chunk);
+    pd.qblocks = (int32_t)ceil_div(nq, (int64_t)kWave * t.q);
+    std::vector<WorkItem> work;
+    for (int32_t b = 0; b < pd.qblocks; ++b)
+        for (int32_t ch = 0; ch < pd.chunks; ++ch) work.push_back(WorkItem{0, b, ch, 0});
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = (size_t)round_up((int64_t)(off + bytes), 256);
+        return o;
+    };
+    const size_t o_q = take(16 * (size_t)nq), o_r = take(16 * (size_t)pd.n_ref_pad);
+    const size_t o_p = take(8 * (size_t)pd.chunks * nq), o_w = take(sizeof(WorkItem) * work.size());
+    const size_t o_d = take(sizeof(PairDesc)), o_f = take(64);
+    char* mem = nullptr;
+    if (hipMalloc(&mem, off) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(STEIN_ICP_E_NOMEM, "device allocation failed");
+    }
+    int rc = STEIN_ICP_OK;
+    int flag = 0;
+    NNArgs a{};
+    a.work = (WorkItem*)(mem + o_w);
+    a.pairs = (PairDesc*)(mem + o_d);
+    a.ref4 = (float4*)(mem + o_r);
+    a.queries = (float4*)(mem + o_q);
+    a.partial = (uint64_t*)(mem + o_p);
+    int* fl = (int*)(mem + o_f);
+    hipError_t e = hipMemsetAsync(fl, 0, 64, s);
+    if (e == hipSuccess) e = hipMemcpyAsync((void*)a.pairs, &pd, sizeof(pd), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((void*)a.work, work.data(), sizeof(WorkItem) * work.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(pack_points_kernel, grid1d(nq, 256), dim3(256), 0, s, q_xyz, nq, nq, (float4*)a.queries, fl);
+        hipLaunchKernelGGL(pack_points_kernel, grid1d(pd.n_ref_pad, 256), dim3(256), 0, s, ref_xyz, n_ref,
+                           pd.n_ref_pad, (float4*)a.ref4, fl);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, fl, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && flag) rc = fail(STEIN_ICP_E_INVALID, "a coordinate is non-finite or above 1e9");
+    if (e == hipSuccess && !rc) {
+        e = launch_nn<false>(t.q, (unsigned)work.size(), a, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(nn_finish_kernel, grid1d(nq, 256), dim3(256), 0, s, a.partial, nq, pd.chunks, idx, d2);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    if (e != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, std::string("stein_icp_nn: ") + hipGetErrorString(e));
+    (void)hipFree(mem);
+    return rc;
+}
+
+int stein_icp_make_schedule(uint64_t seed, int64_t n_src, int32_t m, int32_t rows, int32_t* out_host)
+{
+    if (!out_host) return fail(STEIN_ICP_E_INVALID, "out_host is NULL");
+    if (m < 1 || rows < 1 || n_src < m || n_src > kMaxRef)
+        return fail(STEIN_ICP_E_INVALID, "need 1 <= m <= n_src < 2^31 - 64 and rows >= 1");
+    make_schedule(seed, n_src, m, rows, out_host);
+    return STEIN_ICP_OK;
+}
+
+int stein_icp_make_init(uint64_t seed, int32_t K, double half_trans, double half_rot, const double* centre,
+                        double* out_host)
+{
+    if (!out_host) return fail(STEIN_ICP_E_INVALID, "out_host is NULL");
+    if (K < 1) return fail(STEIN_ICP_E_INVALID, "K must be >= 1");
+    if (!(std::isfinite(half_trans) && half_trans >= 0.0 && std::isfinite(half_rot) && half_rot >= 0.0))
+        return fail(STEIN_ICP_E_INVALID, "half widths must be finite and >= 0");
+    make_init(seed, K, half_trans, half_rot, centre, out_host);
+    return STEIN_ICP_OK;
+}
+
+}  // extern "C"

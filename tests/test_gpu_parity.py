@@ -1,0 +1,296 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded clouds, initial particles and minibatch schedules.
+
+Bars: nearest-neighbour indices and FP32 distances bit-exact (both sides
+decide the argmin in FP32 on the same FP32 queries); particle poses within
+1e-4 m / 1e-4 rad after the fixed iteration count (the stated tolerance);
+per-iteration quantities (gbar, phi, h, theta) also within tighter relative
+bounds derived from FP64 summation-order differences, which is what the
+implementations differ by once the matches agree."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_2106_03287_amd import stein_icp as S
+
+pytestmark = pytest.mark.gpu
+
+POSE_TOL = 1e-4       # m / rad, after the fixed iteration count
+STEP_RTOL = 1e-9      # one iteration from identical state
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def wrapped(d):
+    d = np.array(d, dtype=np.float64, copy=True)
+    d[..., 3:] = np.angle(np.exp(1j * d[..., 3:]))
+    return d
+
+
+def both_configs(prob, opts=None):
+    o = dict(opts or {})
+    g = dict(num_particles=prob.K, batch_size=prob.m, schedule_rows=prob.schedule.shape[0],
+              lr=prob.lr)
+    okw = dict(lr=prob.lr)
+    if o.get("sgd"):
+        g["optimizer"] = S.OPT_SGD
+        okw["optimizer"] = oracle.SGD
+    if "h_fixed" in o:
+        g.update(bandwidth_mode=S.BW_FIXED, fixed_h_trans=o["h_fixed"][0], fixed_h_rot=o["h_fixed"][1])
+        okw.update(bandwidth=oracle.BW_FIXED, h_fixed=tuple(o["h_fixed"]))
+    if "prior" in o:
+        pr = o["prior"]
+        g.update(prior_mode=S.PRIOR_GAUSS_VONMISES, prior_mu=pr["mu"], prior_var_trans=pr["var_trans"],
+                 prior_kappa_rot=pr["kappa_rot"])
+        okw["prior"] = pr
+    for k in ("use_graph", "autotune"):
+        if k in o:
+            g[k] = o[k]
+    gcfg = S.stein_icp_default_config(**g)
+    ocfg = oracle.make_config(prob.K, prob.m, len(prob.pair.src), len(prob.pair.ref), **okw)
+    return gcfg, ocfg
+
+
+def gpu_solver(prob, opts=None):
+    gcfg, _ = both_configs(prob, opts)
+    return S.SteinICP(gcfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0),
+                      dev(prob.schedule))
+
+
+def gpu_run(prob, T, opts=None):
+    sol = gpu_solver(prob, opts)
+    sol.step(T)
+    out = sol.particles().cpu().numpy()[0]
+    sol.close()
+    return out
+
+
+def oracle_run(prob, T, opts=None):
+    _, ocfg = both_configs(prob, opts)
+    st = oracle.State(prob.theta0)
+    oracle.run(ocfg, prob.pair.src, prob.pair.ref, prob.schedule, T, st)
+    return st.theta
+
+
+def assert_poses_close(gpu, ref, tol=POSE_TOL):
+    d = np.abs(wrapped(gpu - ref))
+    print(f"max |dtheta| trans {d[:, :3].max():.3e} rot {d[:, 3:].max():.3e}", flush=True)
+    assert d.max() <= tol
+
+
+# ------------------------------------------------------------------ NN
+
+@pytest.mark.parametrize("nq,M", [(1, 1), (100, 17), (4097, 2000), (777, 20011), (0, 5)])
+def test_nn_bitwise_against_oracle(nq, M):
+    rng = np.random.default_rng(nq * 31 + M)
+    ref = rng.uniform(-1, 1, (M, 3)).astype(np.float32)
+    q = rng.uniform(-1.2, 1.2, (nq, 3)).astype(np.float32)
+    if nq > 10 and M > 10:
+        q[:5] = ref[rng.integers(0, M, 5)]           # exact hits (distance 0)
+    print(f"nn nq={nq} M={M}", flush=True)
+    idx, d2 = S.stein_icp_nn(dev(q).reshape(-1, 3), dev(ref))
+    if nq == 0:
+        return
+    oi, od = oracle.nn_f32(q, ref)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    np.testing.assert_array_equal(d2.cpu().numpy(), od)
+
+
+def test_nn_exact_ties_take_lowest_index():
+    rng = np.random.default_rng(3)
+    ref = rng.integers(-4, 5, (3001, 3)).astype(np.float32)     # many duplicates
+    q = rng.integers(-5, 6, (2500, 3)).astype(np.float32)
+    idx, d2 = S.stein_icp_nn(dev(q), dev(ref))
+    oi, od = oracle.nn_f32(q, ref)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    np.testing.assert_array_equal(d2.cpu().numpy(), od)
+
+
+def test_nn_full_lidar_reference_sampled_queries():
+    prob = synth.make_problem("lidar", 0, K=1, T=1)
+    rng = np.random.default_rng(4)
+    sel = rng.choice(len(prob.pair.src), 3000, replace=False)
+    q = oracle.transform(prob.pair.theta_true, prob.pair.src[sel]).astype(np.float32)
+    idx, d2 = S.stein_icp_nn(dev(q), dev(prob.pair.ref))
+    oi, od = oracle.nn_f32(q, prob.pair.ref)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    np.testing.assert_array_equal(d2.cpu().numpy(), od)
+
+
+# ------------------------------------------------------------------ one iteration
+
+def _one_step_compare(prob, opts=None):
+    sol = gpu_solver(prob, opts)
+    sol.step(1)
+    diag = {k: v.cpu().numpy()[0] for k, v in sol.diagnostics().items()}
+    th_gpu = sol.particles().cpu().numpy()[0]
+    _, _, _, t = sol.get_state()
+    sol.close()
+    _, ocfg = both_configs(prob, opts)
+    st = oracle.State(prob.theta0)
+    od = oracle.step(ocfg, prob.pair.src, prob.pair.ref, prob.schedule[0], st)
+    assert t == 1
+    np.testing.assert_array_equal(diag["match"], od["match"])
+    np.testing.assert_allclose(diag["gbar"], od["gbar"], rtol=STEP_RTOL, atol=1e-13)
+    np.testing.assert_allclose(diag["h"], od["h"], rtol=1e-12)
+    scale = np.abs(od["phi"]).max()
+    np.testing.assert_allclose(diag["phi"], od["phi"], rtol=STEP_RTOL, atol=1e-12 * scale)
+    np.testing.assert_allclose(th_gpu, st.theta, rtol=0, atol=1e-11)
+
+
+def test_one_iteration_cuboid():
+    _one_step_compare(synth.make_problem("cuboid", 0))
+
+
+def test_one_iteration_kinect():
+    _one_step_compare(synth.make_problem("kinect", 0, T=1))
+
+
+def test_one_iteration_lidar_full_size():
+    prob = synth.make_problem("lidar", 0, T=1)
+    print("lidar full-size one iteration: K=300 m=1000 M=100000", flush=True)
+    _one_step_compare(prob)
+
+
+# ------------------------------------------------------------------ free running
+
+def test_cuboid_50_iterations_free_running():
+    prob = synth.make_problem("cuboid", 0)
+    assert_poses_close(gpu_run(prob, prob.T), oracle_run(prob, prob.T))
+
+
+def test_cuboid_other_seeds_free_running():
+    for p in (1, 2):
+        prob = synth.make_problem("cuboid", p)
+        assert_poses_close(gpu_run(prob, prob.T), oracle_run(prob, prob.T))
+
+
+def test_kinect_20_iterations_free_running():
+    prob = synth.make_problem("kinect", 0, T=20)
+    assert_poses_close(gpu_run(prob, prob.T), oracle_run(prob, prob.T))
+
+
+@pytest.mark.parametrize("opts", [
+    {"sgd": True},
+    {"h_fixed": (0.01, 0.05)},
+    {"prior": {"mu": [0.01, -0.02, 0.0, 0.1, -0.1, 0.05], "var_trans": [0.01, 0.02, 0.03],
+               "kappa_rot": [2.0, 4.0, 8.0]}},
+    {"use_graph": 0},
+])
+def test_method_options(opts):
+    prob = synth.make_problem("cuboid", 5, T=10)
+    if opts.get("sgd"):
+        prob.lr = 1e-5
+    print(f"options {opts}", flush=True)
+    assert_poses_close(gpu_run(prob, prob.T, opts), oracle_run(prob, prob.T, opts))
+    _one_step_compare(prob, opts)
+
+
+@pytest.mark.parametrize("K,m", [(1, 100), (2, 100), (3, 1), (4, 37), (1024, 4)])
+def test_particle_and_batch_extremes(K, m):
+    prob = synth.make_problem("cuboid", 6, K=K, m=m, T=4)
+    print(f"K={K} m={m}", flush=True)
+    assert_poses_close(gpu_run(prob, prob.T), oracle_run(prob, prob.T))
+    _one_step_compare(prob)
+
+
+def test_ragged_reference_and_source_sizes():
+    base = synth.cuboid_pair(77, n_src=133, n_ref=77)
+    prob = synth.make_problem("cuboid", 7, K=9, m=133, T=6, pair=base)
+    assert_poses_close(gpu_run(prob, prob.T), oracle_run(prob, prob.T))
+    _one_step_compare(prob)
+
+
+def test_single_reference_point():
+    base = synth.cuboid_pair(78, n_src=64, n_ref=1)
+    prob = synth.make_problem("cuboid", 8, K=5, m=16, T=5, pair=base)
+    assert_poses_close(gpu_run(prob, prob.T), oracle_run(prob, prob.T))
+
+
+# ------------------------------------------------------------------ engine behaviour
+
+def test_graph_direct_and_autotuned_runs_are_bitwise_identical():
+    prob = synth.make_problem("kinect", 1, T=8)
+    a = gpu_run(prob, prob.T, {"use_graph": 1})
+    b = gpu_run(prob, prob.T, {"use_graph": 0})
+    c = gpu_run(prob, prob.T, {"autotune": 1})
+    d = gpu_run(prob, prob.T, {"use_graph": 1})
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(a, c)
+    np.testing.assert_array_equal(a, d)
+
+
+def test_state_round_trip_continues_bitwise():
+    prob = synth.make_problem("cuboid", 9, T=12)
+    full = gpu_run(prob, 12)
+    sol = gpu_solver(prob)
+    sol.step(5)
+    th, mo, ve, t = sol.get_state()
+    sol.close()
+    sol2 = gpu_solver(prob)
+    sol2.set_state(th, mo, ve, t)
+    sol2.step(7)
+    np.testing.assert_array_equal(sol2.particles().cpu().numpy()[0], full)
+    sol2.step(0)
+    np.testing.assert_array_equal(sol2.particles().cpu().numpy()[0], full)
+    sol2.close()
+
+
+def test_batched_context_matches_single_contexts_and_oracle():
+    probs = [synth.make_problem("cuboid", 10 + i, K=16, m=40, T=6,
+                                pair=synth.cuboid_pair(900 + i, n_src=n, n_ref=M))
+             for i, (n, M) in enumerate([(300, 1000), (500, 2003), (64, 77)])]
+    gcfg, _ = both_configs(probs[0])
+    batch = S.SteinICP.batch(gcfg, [dev(p.pair.src) for p in probs], [dev(p.pair.ref) for p in probs],
+                             dev(np.stack([p.theta0 for p in probs])),
+                             [dev(p.schedule) for p in probs])
+    batch.step(6)
+    got = batch.particles().cpu().numpy()
+    batch.close()
+    for i, p in enumerate(probs):
+        np.testing.assert_array_equal(got[i], gpu_run(p, 6))
+        assert_poses_close(got[i], oracle_run(p, 6))
+
+
+def test_library_drawn_particles_and_schedule():
+    prob = synth.make_problem("cuboid", 11, T=5)
+    cfg = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m, schedule_rows=5,
+                                     lr=prob.lr, seed=1234)
+    sol = S.SteinICP(cfg, dev(prob.pair.src), dev(prob.pair.ref))
+    th0 = sol.particles().cpu().numpy()[0]
+    np.testing.assert_array_equal(th0, S.stein_icp_make_init(1234, prob.K, 0.2, np.pi / 4))
+    sol.step(5)
+    got = sol.particles().cpu().numpy()[0]
+    sol.close()
+    prob.theta0 = th0
+    prob.schedule = S.stein_icp_make_schedule(1234, len(prob.pair.src), prob.m, 5)
+    assert_poses_close(got, oracle_run(prob, 5))
+
+
+def test_invalid_device_inputs_are_rejected():
+    prob = synth.make_problem("cuboid", 12, K=4, T=2)
+    gcfg, _ = both_configs(prob)
+    bad = prob.pair.src.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(S.SteinICPError) as e:
+        S.SteinICP(gcfg, dev(bad), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule))
+    assert e.value.code == S.E_INVALID and "non-finite" in str(e.value)
+    sch = prob.schedule.copy()
+    sch[1, 2] = len(prob.pair.src)
+    with pytest.raises(S.SteinICPError) as e:
+        S.SteinICP(gcfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(sch))
+    assert "schedule" in str(e.value)
+    th = prob.theta0.copy()
+    th[0, 0] = np.inf
+    with pytest.raises(S.SteinICPError):
+        S.SteinICP(gcfg, dev(prob.pair.src), dev(prob.pair.ref), dev(th), dev(prob.schedule))
+    big = prob.pair.ref.copy()
+    big[0, 0] = 3e9
+    with pytest.raises(S.SteinICPError):
+        S.stein_icp_nn(dev(prob.pair.src), dev(big))
