@@ -22,8 +22,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Stein-ICP iters/s & particle·point NN queries/s; time-to-MMD≤0.05 vs plain"
-VALU_PEAK_TFLOPS = 78.6     # 256 CUs x 64 FP32 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
+VALU_PEAK_TFLOPS = 157.3    # MI355X FP32 vector peak: 256 CUs x 2.4 GHz x 256 FP32 flop/clk/CU
 FLOPS_PER_PAIR = 9          # 3 sub + 3 mul + 2 add (squared distance) + 1 compare
+NN_SOURCES = ["paper_2106_03287_amd/csrc/nn.hpp", "paper_2106_03287_amd/csrc/common.hpp"]
+
+
+def nn_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in NN_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per NN launch from the committed counter runs, if they were
+    taken on the current kernel source and this workload; else None."""
+    path = os.path.join(ROOT, "profiles", "nn_fp32_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(workload)
+    if not rec or rec.get("source_sha") != nn_source_sha():
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(prob, budget_s=15.0):
@@ -54,6 +75,8 @@ def main():
     ap.add_argument("--workload", default="kinect", choices=["cuboid", "kinect", "lidar"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -63,6 +86,15 @@ def main():
     import torch
     import synth
     from paper_2106_03287_amd import stein_icp as S
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     prob = synth.make_problem(args.workload, 0)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
@@ -101,7 +133,8 @@ def main():
     pairs_per_launch = prob.K * prob.m * M
     achieved = pairs_per_launch * FLOPS_PER_PAIR / (nn_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(prob.name),
                 "kernel": "nn_fp32_kernel", "avg_launch_ms": round(nn_ms, 5),
                 "pair_evals_per_launch": pairs_per_launch}
     sol.close()
@@ -127,6 +160,8 @@ def main():
         "stage_ms_per_iter": {k: round(v / prob.T, 5) for k, v in stage.items()},
         "init_ms": round(init_ms, 2),
         "nn_tiling": tiling,
+        "nn_source_sha": nn_source_sha(),
+        "torch": torch.__version__,
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -162,9 +162,11 @@ int stein_icp_nn_tiling(const stein_icp_ctx *ctx, int32_t *queries_per_lane, int
 
 /* Profiled mode: run n_iters >= 1 iterations with plain launches (no graph),
  * recording HIP events on `hip_stream` around each stage, and return the
- * summed stage times in ms_out[3] (host): nearest neighbours (Eq. 1), mean
- * gradients (Eqs. 4-5), Stein direction plus update (Eqs. 12, 16). Advances
- * the state like stein_icp_step. Blocking. */
+ * summed stage times in ms_out[4] (host): nearest neighbours (Eq. 1), mean
+ * gradients (Eqs. 4-5), median-heuristic bandwidths (Sec. V), Stein direction
+ * plus update (Eqs. 12, 16). Stages run one after another here; a captured
+ * graph overlaps the bandwidths with the first two. Advances the state like
+ * stein_icp_step. Blocking. */
 int stein_icp_stage_times(stein_icp_ctx *ctx, int32_t n_iters, double *ms_out, void *hip_stream);
 
 /* Release the context and its device memory. NULL is a no-op. Blocking

@@ -39,9 +39,16 @@ __global__ __launch_bounds__(kGradThreads) void grad_kernel(GradArgs a)
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < a.m; i += kGradThreads) {
         const int64_t qi = k * a.m + i;
+        // chunk keys, eight loads in flight at a time
         uint64_t key = ~0ull;
         const uint64_t* __restrict__ kp = a.partial + pd.part_off + qi;
-        for (int c = 0; c < pd.chunks; ++c) key = min(key, kp[(int64_t)c * nq]);
+        for (int c0 = 0; c0 < pd.chunks; c0 += 8) {
+            uint64_t kk[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) kk[u] = c0 + u < pd.chunks ? kp[(int64_t)(c0 + u) * nq] : ~0ull;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) key = min(key, kk[u]);
+        }
         const int32_t j = (int32_t)(uint32_t)(key & 0xffffffffull);
         a.match[p * nq + qi] = j;
         const float4 s = a.src4[pd.src_off + a.sched[pd.sched_off + row * a.m + i]];

@@ -126,7 +126,7 @@ struct stein_icp_ctx {
     float4* src4 = nullptr;
     float4* ref4 = nullptr;
     int32_t* sched = nullptr;
-    double *theta = nullptr, *mom = nullptr, *vel = nullptr, *G = nullptr, *gbar = nullptr, *phi = nullptr;
+    double *theta = nullptr, *theta_next = nullptr, *mom = nullptr, *vel = nullptr, *gbar = nullptr, *phi = nullptr;
     double* h = nullptr;
     int64_t* step = nullptr;
     Pose* pose = nullptr;
@@ -137,7 +137,9 @@ struct stein_icp_ctx {
     WorkItem* d_work = nullptr;  // separate allocations: resized by the tuner
     uint64_t* partial = nullptr;
 
-    hipStream_t cap_stream = nullptr;
+    hipStream_t cap_stream = nullptr;   // graph capture
+    hipStream_t side_stream = nullptr;  // bandwidth branch of a captured iteration
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::map<int, hipGraphExec_t> graphs;
 };
 
@@ -297,7 +299,27 @@ NNArgs nn_args(const stein_icp_ctx* c)
     return a;
 }
 
-// Stage 0: nearest neighbours, 1: gradients, 2: Stein direction and update.
+SvgdArgs svgd_args(const stein_icp_ctx* c)
+{
+    SvgdArgs v{};
+    v.pairs = c->d_pairs;
+    v.theta = c->theta;
+    v.theta_next = c->theta_next;
+    v.mom = c->mom;
+    v.vel = c->vel;
+    v.step = c->step;
+    v.gbar = c->gbar;
+    v.phi = c->phi;
+    v.h = c->h;
+    v.dscr = c->dscr;
+    v.pose = c->pose;
+    v.K = c->K;
+    v.prm = svgd_params(c->cfg);
+    return v;
+}
+
+// Stage 0: nearest neighbours, 1: gradients, 2: bandwidths, 3: Stein
+// direction, update and commit.
 hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
 {
     if (stage == 0) return launch_nn<true>(c->tiling.q, (unsigned)c->work.size(), nn_args(c), s);
@@ -318,31 +340,45 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
     hipLaunchKernelGGL(grad_kernel, dim3((unsigned)((int64_t)c->P * c->K)), dim3(kGradThreads), 0, s, g);
     return hipGetLastError();
     }
-    SvgdArgs v{};
-    v.pairs = c->d_pairs;
-    v.theta = c->theta;
-    v.mom = c->mom;
-    v.vel = c->vel;
-    v.step = c->step;
-    v.gbar = c->gbar;
-    v.G = c->G;
-    v.phi = c->phi;
-    v.h = c->h;
-    v.dscr = c->dscr;
-    v.pose = c->pose;
-    v.K = c->K;
-    v.prm = svgd_params(c->cfg);
-    hipLaunchKernelGGL(svgd_update_kernel, dim3((unsigned)c->P), dim3(kSvgdThreads), 0, s, v);
+    const SvgdArgs v = svgd_args(c);
+    if (stage == 2) {
+        hipLaunchKernelGGL(svgd_bandwidth_kernel, dim3((unsigned)c->P, 2), dim3(kSvgdThreads),
+                           bandwidth_lds_bytes(c->K), s, v);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(svgd_phi_update_kernel, dim3((unsigned)ceil_div(c->K, 4), (unsigned)c->P), dim3(256), 0, s, v);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(svgd_finish_kernel, dim3((unsigned)c->P), dim3(256), 0, s, v);
     return hipGetLastError();
 }
 
+constexpr int kStages = 4;  // nearest neighbours, gradients, bandwidths, direction + update
+
+// One iteration in stream order on `s`.
 hipError_t enqueue_iteration(const stein_icp_ctx* c, hipStream_t s)
 {
-    for (int st = 0; st < 3; ++st) {
+    for (int st = 0; st < kStages; ++st) {
         const hipError_t e = enqueue_stage(c, st, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// One iteration for graph capture: the bandwidths depend only on the current
+// particles, so they run on a forked branch beside the nearest-neighbour and
+// gradient kernels and join before the direction + update.
+hipError_t enqueue_iteration_forked(const stein_icp_ctx* c, hipStream_t s)
+{
+    hipError_t e = hipEventRecord(c->ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->side_stream, c->ev_fork, 0);
+    if (e == hipSuccess) e = enqueue_stage(c, 2, c->side_stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->side_stream);
+    if (e == hipSuccess) e = enqueue_stage(c, 0, s);
+    if (e == hipSuccess) e = enqueue_stage(c, 1, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_join, 0);
+    if (e == hipSuccess) e = enqueue_stage(c, 3, s);
+    return e;
 }
 
 int get_graph(stein_icp_ctx* c, int len, hipGraphExec_t* out)
@@ -353,9 +389,12 @@ int get_graph(stein_icp_ctx* c, int len, hipGraphExec_t* out)
         return STEIN_ICP_OK;
     }
     if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    if (!c->side_stream) HIP_TRY(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+    if (!c->ev_fork) HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    if (!c->ev_join) HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int i = 0; i < len && e == hipSuccess; ++i) e = enqueue_iteration(c, c->cap_stream);
+    for (int i = 0; i < len && e == hipSuccess; ++i) e = enqueue_iteration_forked(c, c->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -449,6 +488,9 @@ void free_ctx(stein_icp_ctx* c)
     (void)hipDeviceSynchronize();
     for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->arena) (void)hipFree(c->arena);
     if (c->d_work) (void)hipFree(c->d_work);
     if (c->partial) (void)hipFree(c->partial);
@@ -504,6 +546,8 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
         c->pairs.push_back(pd);
     }
     c->tiling = default_tiling(c->pairs, nq);
+    HIP_TRY(hipFuncSetAttribute((const void*)svgd_bandwidth_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bandwidth_lds_bytes(K)));
     const int64_t PK6 = (int64_t)P * K * 6;
     const int64_t npairs2 = K >= 2 ? (int64_t)K * (K - 1) : 1;
     size_t off = 0;
@@ -516,8 +560,8 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     const size_t o_src = take(sizeof(float4) * so);
     const size_t o_ref = take(sizeof(float4) * ro);
     const size_t o_sched = take(sizeof(int32_t) * (size_t)P * rows * m);
-    const size_t o_theta = take(8 * PK6), o_mom = take(8 * PK6), o_vel = take(8 * PK6);
-    const size_t o_G = take(8 * PK6), o_gbar = take(8 * PK6), o_phi = take(8 * PK6);
+    const size_t o_theta = take(8 * PK6), o_thn = take(8 * PK6), o_mom = take(8 * PK6), o_vel = take(8 * PK6);
+    const size_t o_gbar = take(8 * PK6), o_phi = take(8 * PK6);
     const size_t o_h = take(8 * 2 * (size_t)P);
     const size_t o_step = take(8 * (size_t)P);
     const size_t o_pose = take(sizeof(Pose) * (size_t)P * K);
@@ -534,9 +578,9 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     c->ref4 = (float4*)(c->arena + o_ref);
     c->sched = (int32_t*)(c->arena + o_sched);
     c->theta = (double*)(c->arena + o_theta);
+    c->theta_next = (double*)(c->arena + o_thn);
     c->mom = (double*)(c->arena + o_mom);
     c->vel = (double*)(c->arena + o_vel);
-    c->G = (double*)(c->arena + o_G);
     c->gbar = (double*)(c->arena + o_gbar);
     c->phi = (double*)(c->arena + o_phi);
     c->h = (double*)(c->arena + o_h);
@@ -748,34 +792,33 @@ int stein_icp_stage_times(stein_icp_ctx* ctx, int32_t n_iters, double* ms_out, v
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(s, &st));
     if (st != hipStreamCaptureStatusNone) return fail(STEIN_ICP_E_STATE, "stream is capturing");
-    std::vector<hipEvent_t> ev((size_t)n_iters * 4, nullptr);
+    std::vector<hipEvent_t> ev((size_t)n_iters * (kStages + 1), nullptr);
     int rc = STEIN_ICP_OK;
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, "hipEventCreate failed");
+    const size_t W = kStages + 1;
     for (int32_t i = 0; i < n_iters && rc == STEIN_ICP_OK; ++i) {
-        hipEvent_t* e = ev.data() + 4 * (size_t)i;
+        hipEvent_t* e = ev.data() + W * (size_t)i;
         hipError_t err = hipEventRecord(e[0], s);
-        if (err == hipSuccess) err = enqueue_stage(ctx, 0, s);
-        if (err == hipSuccess) err = hipEventRecord(e[1], s);
-        if (err == hipSuccess) err = enqueue_stage(ctx, 1, s);
-        if (err == hipSuccess) err = hipEventRecord(e[2], s);
-        if (err == hipSuccess) err = enqueue_stage(ctx, 2, s);
-        if (err == hipSuccess) err = hipEventRecord(e[3], s);
+        for (int st = 0; st < kStages && err == hipSuccess; ++st) {
+            err = enqueue_stage(ctx, st, s);
+            if (err == hipSuccess) err = hipEventRecord(e[st + 1], s);
+        }
         if (err != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, std::string("profiled step: ") + hipGetErrorString(err));
     }
     if (rc == STEIN_ICP_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, "sync failed");
-    double t[3] = {0, 0, 0};
+    double t[kStages] = {0, 0, 0, 0};
     for (int32_t i = 0; i < n_iters && rc == STEIN_ICP_OK; ++i)
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < kStages; ++k) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, ev[4 * (size_t)i + k], ev[4 * (size_t)i + k + 1]) != hipSuccess)
+            if (hipEventElapsedTime(&ms, ev[W * (size_t)i + k], ev[W * (size_t)i + k + 1]) != hipSuccess)
                 rc = fail(STEIN_ICP_E_DEVICE, "hipEventElapsedTime failed");
             t[k] += ms;
         }
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
     if (rc == STEIN_ICP_OK)
-        for (int k = 0; k < 3; ++k) ms_out[k] = t[k];
+        for (int k = 0; k < kStages; ++k) ms_out[k] = t[k];
     return rc;
 }
 

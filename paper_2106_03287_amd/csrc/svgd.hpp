@@ -1,17 +1,26 @@
-// Stein direction (Eq. 16) and particle update (Eq. 12 with Adam), one
-// workgroup of 1024 threads per pair.
+// Stein direction (Eq. 16) and particle update (Eq. 12 with Adam).
 //
-//  1. G_k = -N gbar_k + grad log p(theta_k)  (Eq. 10 with Eqs. 14-15).
-//  2. Median heuristic: the K(K-1)/2 squared distances between distinct
-//     particles (translation, and wrapped rotation of Eq. 17) are written to
-//     a scratch array and the middle order statistics are found exactly by a
-//     block-wide radix select over their IEEE-754 bit patterns (non-negative
-//     doubles order like unsigned integers): 12-bit digits, 4096-bin LDS
-//     histogram, early exit once the selected bin holds one value.
-//  3. phi_k = (1/K) sum_l [G_l k(l,k) + grad_{theta_l} k(l,k)] for the
-//     translation and rotation blocks, one wavefront per particle k, lanes
-//     over l, fixed-shape shuffle reduction.
-//  4. Adam on -phi (or theta += lr phi), then the next iteration's poses.
+// Three kernels per iteration:
+//  * svgd_bandwidth_kernel, one 1024-thread workgroup per (pair, block):
+//    block 0 the translation kernel, block 1 the wrapped-angle rotation
+//    kernel of Eq. 17. The median heuristic h = med^2 / ln K needs the middle
+//    order statistics of the K(K-1)/2 distances between distinct particles,
+//    found exactly: the distances are stored as 16-bit monotone keys in LDS
+//    (K up to about 345), a 4096-bin integer histogram of the key range
+//    narrows them to one bin in at most two rounds, and the exact FP64
+//    distances of that bin's few pairs are recomputed and ranked by counting.
+//    Larger K keep FP64 distances in global memory and bin by value. A radix
+//    select over IEEE-754 bit patterns covers the degenerate cases. The
+//    kernel depends only on the particles, so it runs beside the
+//    nearest-neighbour stage.
+//  * svgd_phi_update_kernel, one wavefront per particle k:
+//    phi_k = (1/K) sum_l [G_l k(l,k) + grad_{theta_l} k(l,k)] with
+//    G_l = -N gbar_l + grad log p(theta_l) (Eq. 10 with Eqs. 14-15), lanes over
+//    l and a fixed-shape shuffle reduction; then Adam on -phi (or
+//    theta += lr phi) for particle k, written to a second buffer (other
+//    wavefronts still read the current particles), and the particle's next
+//    pose.
+//  * svgd_finish_kernel: commits the new particles and advances the step.
 #pragma once
 
 #include "common.hpp"
@@ -30,23 +39,28 @@ struct SvgdParams {
 
 struct SvgdArgs {
     const PairDesc* pairs;
-    double* theta;
+    double* theta;        // current particles, K x 6 per pair
+    double* theta_next;   // updated particles before the commit
     double* mom;
     double* vel;
     int64_t* step;
     const double* gbar;
-    double* G;
     double* phi;
-    double* h;
-    double* dscr;     // 2 * K(K-1)/2 per pair
+    double* h;            // 2 per pair
+    double* dscr;         // K(K-1)/2 per pair and block, for K above the register limit
     Pose* pose;
     int32_t K, pad_;
     SvgdParams prm;
 };
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr int kSvgdWaves = kSvgdThreads / kWave;
+constexpr int kCandCap = 1024;   // values ranked directly once a bin holds this few
+constexpr int kUnroll = 8;       // global loads in flight per thread in a pass
 
-// Wrapped angle difference in (-pi, pi]: x - 2 pi round(x / 2 pi).
+// Wrapped angle difference in (-pi, pi]: x - 2 pi round(x / 2 pi). Odd:
+// wrap_pi(-x) == -wrap_pi(x) exactly (round-half-even and the products are
+// sign-symmetric).
 __device__ __forceinline__ double wrap_pi(double x)
 {
 #pragma clang fp contract(off)
@@ -68,15 +82,85 @@ __device__ __forceinline__ double dist2_rot(const double* __restrict__ a, const 
     return (d0 * d0 + d1 * d1) + d2 * d2;
 }
 
+// Start of row k of the row-major upper triangle (pairs (k, l), l > k).
+__device__ __forceinline__ int64_t tri_row(int k, int K) { return (int64_t)k * K - (int64_t)k * (k + 1) / 2; }
+
+// Pair (k, l), k < l, of upper-triangle index q.
+__device__ __forceinline__ void tri_pair(int64_t q, int K, int& k, int& l)
+{
+    const double b = 2.0 * K - 1.0;
+    int kk = (int)floor((b - sqrt(b * b - 8.0 * (double)q)) * 0.5);
+    kk = max(0, min(kk, K - 2));
+    while (kk > 0 && tri_row(kk, K) > q) --kk;
+    while (kk < K - 2 && tri_row(kk + 1, K) <= q) ++kk;
+    k = kk;
+    l = (int)(q - tri_row(kk, K)) + kk + 1;
+}
+
 struct SelectShared {
     uint32_t hist[4096];
-    uint32_t wsum[kSvgdThreads / kWave];
+    double cand[kCandCap];
+    uint32_t wsum[kSvgdWaves];
+    double wmin[kSvgdWaves], wmax[kSvgdWaves];
+    double dres;
     uint64_t u64a, u64b;
-    uint32_t bin, before, count, found;
+    uint32_t bin, before, count, ncand, found;
 };
 
-// Inclusive scan of one value per thread over the workgroup; returns the
-// exclusive prefix.
+// Exact squared distance of upper-triangle pair q from the particles in LDS.
+__device__ __forceinline__ double pair_dist(int64_t q, int K, int rot, const double* th)
+{
+    int k, l;
+    tri_pair(q, K, k, l);
+    return rot ? dist2_rot(th + 6 * k, th + 6 * l) : dist2_trans(th + 6 * k, th + 6 * l);
+}
+
+// 16-bit order key of a non-negative distance: the top half of its FP32 bit
+// pattern. Both roundings are monotone, so key(x) < key(y) implies x < y and
+// the pairs whose keys lie in [lo, hi] form a contiguous run of the exact
+// order.
+__device__ __forceinline__ uint16_t order_key(double x) { return (uint16_t)(__float_as_uint((float)x) >> 16); }
+
+// Exact distances of the pairs whose LDS key lies in [lo, hi], recomputed on
+// each visit (radix fallback for runs of equal keys).
+struct KeyRunValues {
+    const uint16_t* key;
+    int64_t n;
+    uint32_t lo, hi;
+    int K, rot;
+    const double* th;
+    template <class F>
+    __device__ __forceinline__ void visit(F&& f) const
+    {
+        for (int64_t q = threadIdx.x; q < n; q += kSvgdThreads) {
+            const uint32_t x = key[q];
+            if (x >= lo && x <= hi) f(pair_dist(q, K, rot, th));
+        }
+    }
+};
+
+// Values in global memory, visited with kUnroll loads in flight per thread.
+struct GlobalValues {
+    const double* v;
+    int64_t n;
+    template <class F>
+    __device__ __forceinline__ void visit(F&& f) const
+    {
+        for (int64_t base = threadIdx.x; base < n; base += (int64_t)kUnroll * kSvgdThreads) {
+            double x[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t i = base + (int64_t)u * kSvgdThreads;
+                x[u] = i < n ? v[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (base + (int64_t)u * kSvgdThreads < n) f(x[u]);
+        }
+    }
+};
+
+// Exclusive prefix of one value per thread over the workgroup.
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, SelectShared& sh)
 {
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
@@ -94,212 +178,402 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, SelectShared& sh)
     return before + x - v;
 }
 
-// Exact rank-r order statistic (0-based) of n non-negative doubles in global
-// memory, by radix selection on their bit patterns.
-__device__ inline uint64_t block_select(const double* __restrict__ v, int64_t n, int64_t r,
-                                        SelectShared& sh)
+// Find the histogram bin holding rank r (0-based) of nb <= 4096 bins; sets
+// sh.bin / sh.before / sh.count. Four consecutive bins per thread.
+__device__ __forceinline__ void find_rank_bin(uint32_t nb, int64_t r, SelectShared& sh)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        sh.bin = 0;
+        sh.before = 0;
+        sh.count = 0;
+    }
+    uint32_t c[4], loc = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t bin = 4 * tid + b;
+        c[b] = bin < nb ? sh.hist[bin] : 0u;
+        loc += c[b];
+    }
+    const uint32_t excl = block_exclusive_scan(loc, sh);
+    if ((int64_t)excl <= r && r < (int64_t)(excl + loc)) {
+        uint32_t run = excl;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if ((int64_t)run <= r && r < (int64_t)(run + c[b])) {
+                sh.bin = 4 * tid + b;
+                sh.before = run;
+                sh.count = c[b];
+            }
+            run += c[b];
+        }
+    }
+    __syncthreads();
+}
+
+// Block-wide min and max over the values accepted by `pred`.
+template <class Src, class P>
+__device__ __forceinline__ void block_minmax(const Src& src, P&& pred, SelectShared& sh, double& mn, double& mx)
+{
+    double a = __builtin_inf(), b = -__builtin_inf();
+    src.visit([&](double x) {
+        if (pred(x)) {
+            a = fmin(a, x);
+            b = fmax(b, x);
+        }
+    });
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        a = fmin(a, __shfl_xor(a, o));
+        b = fmax(b, __shfl_xor(b, o));
+    }
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh.wmin[wave] = a;
+        sh.wmax[wave] = b;
+    }
+    __syncthreads();
+    mn = sh.wmin[0];
+    mx = sh.wmax[0];
+    for (int w = 1; w < kSvgdWaves; ++w) {
+        mn = fmin(mn, sh.wmin[w]);
+        mx = fmax(mx, sh.wmax[w]);
+    }
+    __syncthreads();
+}
+
+// Exact rank-r order statistic of non-negative doubles by radix selection on
+// their bit patterns (any finite or infinite values).
+template <class Src>
+__device__ __forceinline__ double select_radix(const Src& src, int64_t r, SelectShared& sh)
 {
     const int tid = threadIdx.x;
     uint64_t prefix = 0, mask = 0;
-    const int shifts[6] = {52, 40, 28, 16, 4, 0};
-    const int widths[6] = {12, 12, 12, 12, 12, 4};
+    // digits: bits 63..52, 51..40, 39..28, 27..16, 15..4, 3..0
     for (int pass = 0; pass < 6; ++pass) {
-        const int sft = shifts[pass];
-        const uint32_t nb = 1u << widths[pass];
+        const int sft = pass < 5 ? 52 - 12 * pass : 0;
+        const uint32_t nb = pass < 5 ? 4096u : 16u;
         const uint64_t dmask = (uint64_t)(nb - 1);
         for (uint32_t b = tid; b < 4096; b += kSvgdThreads) sh.hist[b] = 0;
         __syncthreads();
-        for (int64_t i = tid; i < n; i += kSvgdThreads) {
-            const uint64_t u = (uint64_t)__double_as_longlong(v[i]);
+        src.visit([&](double x) {
+            const uint64_t u = (uint64_t)__double_as_longlong(x);
             if ((u & mask) == prefix) atomicAdd(&sh.hist[(u >> sft) & dmask], 1u);
-        }
+        });
         __syncthreads();
-        // four consecutive bins per thread
-        uint32_t c[4], loc = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint32_t bin = 4 * tid + b;
-            c[b] = bin < nb ? sh.hist[bin] : 0u;
-            loc += c[b];
-        }
-        const uint32_t excl = block_exclusive_scan(loc, sh);
-        if ((int64_t)excl <= r && r < (int64_t)(excl + loc)) {
-            uint32_t run = excl;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                if ((int64_t)run <= r && r < (int64_t)(run + c[b])) {
-                    sh.bin = 4 * tid + b;
-                    sh.before = run;
-                    sh.count = c[b];
-                }
-                run += c[b];
-            }
-        }
-        __syncthreads();
+        find_rank_bin(nb, r, sh);
         prefix |= (uint64_t)sh.bin << sft;
         mask |= dmask << sft;
         r -= sh.before;
         const uint32_t cnt = sh.count;
         __syncthreads();
         if (cnt == 1 && pass < 5) {
-            for (int64_t i = tid; i < n; i += kSvgdThreads) {
-                const uint64_t u = (uint64_t)__double_as_longlong(v[i]);
+            src.visit([&](double x) {
+                const uint64_t u = (uint64_t)__double_as_longlong(x);
                 if ((u & mask) == prefix) sh.u64a = u;
-            }
+            });
             __syncthreads();
             const uint64_t res = sh.u64a;
             __syncthreads();
+            return __longlong_as_double((long long)res);
+        }
+    }
+    return __longlong_as_double((long long)prefix);
+}
+
+// Exact rank-r order statistic (0-based) of non-negative doubles.
+template <class Src>
+__device__ __forceinline__ double block_select(const Src& src, int64_t r, SelectShared& sh)
+{
+    const int tid = threadIdx.x;
+    double lo, hi;
+    block_minmax(src, [](double) { return true; }, sh, lo, hi);
+    // every round shrinks the range by the bin count; the bound only matters
+    // for non-finite inputs, which go to the bit-pattern radix select
+    for (int round = 0; round < 64; ++round) {
+        if (lo == hi) return lo;                       // every candidate equal
+        const double width = hi - lo;
+        const double scale = 4096.0 / width;
+        if (!(width < __builtin_inf()) || !(scale < __builtin_inf())) break;
+        auto inside = [&](double x) { return x >= lo && x <= hi; };
+        auto bin_of = [&](double x) { return min(4095, (int)((x - lo) * scale)); };
+        for (uint32_t b = tid; b < 4096; b += kSvgdThreads) sh.hist[b] = 0;
+        if (tid == 0) sh.ncand = 0;
+        __syncthreads();
+        src.visit([&](double x) {
+            if (inside(x)) atomicAdd(&sh.hist[bin_of(x)], 1u);
+        });
+        __syncthreads();
+        find_rank_bin(4096, r, sh);
+        const int b = (int)sh.bin;
+        const uint32_t cnt = sh.count;
+        r -= sh.before;
+        __syncthreads();
+        auto in_bin = [&](double x) { return inside(x) && bin_of(x) == b; };
+        if (cnt <= kCandCap) {
+            src.visit([&](double x) {
+                if (in_bin(x)) {
+                    const uint32_t slot = atomicAdd(&sh.ncand, 1u);
+                    if (slot < kCandCap) sh.cand[slot] = x;
+                }
+            });
+            __syncthreads();
+            const uint32_t c = min(sh.ncand, (uint32_t)kCandCap);
+            for (uint32_t t = tid; t < c; t += kSvgdThreads) {
+                const double x = sh.cand[t];
+                uint32_t less = 0, leq = 0;
+                for (uint32_t j = 0; j < c; ++j) {
+                    const double y = sh.cand[j];
+                    less += y < x;
+                    leq += y <= x;
+                }
+                if ((int64_t)less <= r && r < (int64_t)leq) sh.dres = x;   // same value for all writers
+            }
+            __syncthreads();
+            const double res = sh.dres;
+            __syncthreads();
             return res;
         }
+        // narrow to the selected bin: the monotone bin map makes the bin's
+        // values exactly those in [min, max] of the bin
+        block_minmax(src, in_bin, sh, lo, hi);
     }
-    return prefix;
+    return select_radix(src, r, sh);
 }
 
-// Median-heuristic bandwidth over n = K(K-1)/2 squared distances.
-__device__ inline double median_bandwidth(const double* __restrict__ v, int64_t n, int K, SelectShared& sh)
+// Exact order statistics r and, if `want_next`, r + 1 (0-based) of the n
+// pair distances whose 16-bit keys are in LDS. Integer binning of the key
+// range narrows the candidates to one bin (at most two rounds from 65536
+// key values); the exact FP64 distances of the final candidates are
+// recomputed and ranked by counting. *got_next is false when r + 1 lies
+// outside the final candidates.
+__device__ inline double select_keyed(const uint16_t* key, int64_t n, int64_t r, bool want_next, int K, int rot,
+                                      const double* th, SelectShared& sh, double* next, bool* got_next)
 {
-    const int64_t ra = (n - 1) / 2, rb = n / 2;
-    const uint64_t ua = block_select(v, n, ra, sh);
-    uint64_t ub = ua;
-    if (rb != ra) {
-        if (threadIdx.x == 0) {
-            sh.u64b = ~0ull;
-            sh.found = 0;
+    const int tid = threadIdx.x;
+    *got_next = false;
+    uint32_t lo = 0, hi = 0xffffu;
+    for (int round = 0; round < 4; ++round) {
+        const uint32_t range = hi - lo + 1;
+        int sft = 0;
+        while ((range - 1) >> sft >= 4096u) ++sft;
+        for (uint32_t i = tid; i < 4096; i += kSvgdThreads) sh.hist[i] = 0;
+        __syncthreads();
+        for (int64_t q = tid; q < n; q += kSvgdThreads) {
+            const uint32_t x = key[q];
+            if (x >= lo && x <= hi) atomicAdd(&sh.hist[(x - lo) >> sft], 1u);
         }
         __syncthreads();
-        uint32_t le = 0;
-        uint64_t gt = ~0ull;
-        for (int64_t i = threadIdx.x; i < n; i += kSvgdThreads) {
-            const uint64_t u = (uint64_t)__double_as_longlong(v[i]);
-            if (u <= ua) ++le;
-            else gt = min(gt, u);
-        }
-        atomicAdd(&sh.found, le);
-        atomicMin((unsigned long long*)&sh.u64b, (unsigned long long)gt);
+        find_rank_bin(4096, r, sh);
+        const uint32_t b = sh.bin, cnt = sh.count;
+        r -= sh.before;
         __syncthreads();
-        ub = ((int64_t)sh.found >= rb + 1) ? ua : sh.u64b;
-        __syncthreads();
-    }
-    const double a = sqrt(__longlong_as_double((long long)ua));
-    const double b = sqrt(__longlong_as_double((long long)ub));
-    const double med = (ra == rb) ? a : 0.5 * (a + b);
-    if (!(med > 0.0)) return 1.0;
-    return (med * med) / log((double)K);
-}
-
-__global__ __launch_bounds__(kSvgdThreads) void svgd_update_kernel(SvgdArgs a)
-{
-    const int64_t p = blockIdx.x;
-    const int K = a.K;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
-    const PairDesc pd = a.pairs[p];
-    double* __restrict__ th = a.theta + p * K * 6;
-    double* __restrict__ G = a.G + p * K * 6;
-    const double* __restrict__ gb = a.gbar + p * K * 6;
-    const int64_t t_old = a.step[p];
-    __shared__ SelectShared sh;
-    __shared__ double hh[2];
-
-    // 1. posterior score per particle
-    for (int e = tid; e < 6 * K; e += kSvgdThreads) {
-        const int d = e % 6;
-        double pg = 0.0;
-        if (a.prm.prior == 1) {
-            const double x = th[e] - a.prm.prior_mu[d];
-            pg = d < 3 ? -x / a.prm.prior_var[d] : -a.prm.prior_kappa[d - 3] * sin(x);
-        }
-        G[e] = -(double)pd.n_scale * gb[e] + pg;
-    }
-
-    // 2. bandwidths
-    double ht = 1.0, hr = 1.0;
-    if (a.prm.bandwidth == 1) {
-        ht = a.prm.h_fixed_t;
-        hr = a.prm.h_fixed_r;
-    } else if (K >= 2) {
-        const int64_t np = (int64_t)K * (K - 1) / 2;
-        double* __restrict__ dt = a.dscr + p * 2 * np;
-        double* __restrict__ dr = dt + np;
-        for (int64_t e = tid; e < (int64_t)K * K; e += kSvgdThreads) {
-            const int k = (int)(e / K), l = (int)(e - (int64_t)k * K);
-            if (l > k) {
-                const int64_t lin = (int64_t)k * K - (int64_t)k * (k + 1) / 2 + (l - k - 1);
-                dt[lin] = dist2_trans(th + 6 * k, th + 6 * l);
-                dr[lin] = dist2_rot(th + 6 * k, th + 6 * l);
+        const uint32_t nlo = lo + (b << sft);
+        const uint32_t nhi = min(hi, nlo + (1u << sft) - 1u);
+        if (cnt <= (uint32_t)kCandCap) {
+            if (tid == 0) {
+                sh.ncand = 0;
+                sh.found = 0;
             }
+            __syncthreads();
+            for (int64_t q = tid; q < n; q += kSvgdThreads) {
+                const uint32_t x = key[q];
+                if (x >= nlo && x <= nhi) {
+                    const uint32_t slot = atomicAdd(&sh.ncand, 1u);
+                    if (slot < kCandCap) sh.cand[slot] = pair_dist(q, K, rot, th);
+                }
+            }
+            __syncthreads();
+            const uint32_t c = min(sh.ncand, (uint32_t)kCandCap);
+            for (uint32_t t = tid; t < c; t += kSvgdThreads) {
+                const double x = sh.cand[t];
+                uint32_t less = 0, leq = 0;
+                for (uint32_t j = 0; j < c; ++j) {
+                    const double y = sh.cand[j];
+                    less += y < x;
+                    leq += y <= x;
+                }
+                if ((int64_t)less <= r && r < (int64_t)leq) sh.dres = x;   // same value for all writers
+                if (want_next && (int64_t)less <= r + 1 && r + 1 < (int64_t)leq) {
+                    sh.wmax[0] = x;
+                    sh.found = 1;
+                }
+            }
+            __syncthreads();
+            const double res = sh.dres;
+            *got_next = sh.found != 0;
+            *next = sh.wmax[0];
+            __syncthreads();
+            return res;
+        }
+        lo = nlo;
+        hi = nhi;
+        if (lo == hi) break;    // one key value held by more than kCandCap pairs
+    }
+    return select_radix(KeyRunValues{key, n, lo, hi, K, rot, th}, r, sh);
+}
+
+// Pair distances of the bandwidth kernel are kept as 16-bit keys in LDS up
+// to this many pairs (K up to about 345); beyond, as FP64 in global memory.
+constexpr int64_t kMaxKeyedPairs = 60000;
+
+// grid (pairs, 2), 1024 threads. blockIdx.y: 0 translation, 1 rotation.
+// Dynamic LDS: K x 6 particles (FP64) followed by the 16-bit pair keys.
+__global__ __launch_bounds__(kSvgdThreads) void svgd_bandwidth_kernel(SvgdArgs a)
+{
+    extern __shared__ double dyn[];
+    const int64_t p = blockIdx.x;
+    const int rot = blockIdx.y;
+    const int K = a.K;
+    const int tid = threadIdx.x;
+    if (a.prm.bandwidth == 1 || K < 2) {
+        if (tid == 0) a.h[2 * p + rot] = a.prm.bandwidth == 1 ? (rot ? a.prm.h_fixed_r : a.prm.h_fixed_t) : 1.0;
+        return;
+    }
+    __shared__ SelectShared sh;
+    double* th = dyn;
+    for (int e = tid; e < 6 * K; e += kSvgdThreads) th[e] = a.theta[p * K * 6 + e];
+    __syncthreads();
+    const int64_t np = (int64_t)K * (K - 1) / 2;
+    const int64_t ra = (np - 1) / 2, rb = np / 2;
+    double va, vb;
+    if (np <= kMaxKeyedPairs) {
+        uint16_t* key = reinterpret_cast<uint16_t*>(dyn + 6 * K);
+        for (int k = tid >> 6; k < K; k += kSvgdWaves) {
+            const int64_t row = tri_row(k, K);
+            for (int l = k + 1 + (tid & (kWave - 1)); l < K; l += kWave)
+                key[row + (l - k - 1)] = order_key(rot ? dist2_rot(th + 6 * k, th + 6 * l)
+                                                       : dist2_trans(th + 6 * k, th + 6 * l));
+        }
+        __syncthreads();
+        bool got = false;
+        va = select_keyed(key, np, ra, rb != ra, K, rot, th, sh, &vb, &got);
+        if (rb == ra) {
+            vb = va;
+        } else if (!got) {
+            double unused;
+            vb = select_keyed(key, np, rb, false, K, rot, th, sh, &unused, &got);
+        }
+    } else {
+        double* d = a.dscr + (p * 2 + rot) * np;
+        for (int k = tid >> 6; k < K; k += kSvgdWaves) {
+            const int64_t row = tri_row(k, K);
+            for (int l = k + 1 + (tid & (kWave - 1)); l < K; l += kWave)
+                d[row + (l - k - 1)] = rot ? dist2_rot(th + 6 * k, th + 6 * l) : dist2_trans(th + 6 * k, th + 6 * l);
         }
         __threadfence_block();
         __syncthreads();
-        ht = median_bandwidth(dt, np, K, sh);
-        hr = median_bandwidth(dr, np, K, sh);
-    }
-    __threadfence_block();
-    __syncthreads();
-
-    // 3. Stein direction, one wavefront per particle
-    const int nwaves = kSvgdThreads / kWave;
-    for (int k = wave; k < K; k += nwaves) {
-        const double* tk = th + 6 * k;
-        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int l = lane; l < K; l += kWave) {
-            const double* tl = th + 6 * l;
-            const double* Gl = G + 6 * l;
-            const double kt = exp(-dist2_trans(tl, tk) / ht);
-            const double kr = exp(-dist2_rot(tl, tk) / hr);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                acc[d] += Gl[d] * kt + (-(2.0 / ht) * (tl[d] - tk[d]) * kt);
-                acc[3 + d] += Gl[3 + d] * kr + (-(2.0 / hr) * wrap_pi(tl[3 + d] - tk[3 + d]) * kr);
-            }
-        }
-#pragma unroll
-        for (int d = 0; d < 6; ++d) {
-            double x = acc[d];
-#pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
-            acc[d] = x;
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (int d = 0; d < 6; ++d) a.phi[(p * K + k) * 6 + d] = acc[d] / K;
-        }
+        const GlobalValues src{d, np};
+        va = block_select(src, ra, sh);
+        vb = rb == ra ? va : block_select(src, rb, sh);
     }
     if (tid == 0) {
-        a.h[2 * p] = ht;
-        a.h[2 * p + 1] = hr;
+        const double med = (ra == rb) ? sqrt(va) : 0.5 * (sqrt(va) + sqrt(vb));
+        a.h[2 * p + rot] = med > 0.0 ? (med * med) / log((double)K) : 1.0;
     }
-    __threadfence_block();
-    __syncthreads();
+}
 
-    // 4. update
-    const int64_t t_new = t_old + 1;
-    const double* __restrict__ ph = a.phi + p * K * 6;
-    if (a.prm.optimizer == 1) {
-        for (int e = tid; e < 6 * K; e += kSvgdThreads) {
-#pragma clang fp contract(off)
-            th[e] = th[e] + a.prm.lr * ph[e];
+// Dynamic LDS bytes of svgd_bandwidth_kernel.
+inline size_t bandwidth_lds_bytes(int K)
+{
+    const int64_t np = (int64_t)K * (K - 1) / 2;
+    size_t b = 48 * (size_t)K;
+    if (np <= kMaxKeyedPairs) b += 2 * (size_t)np;
+    return (b + 15) / 16 * 16;
+}
+
+// grid (ceil(K / 4), pairs), 256 threads: one wavefront per particle.
+__global__ __launch_bounds__(256) void svgd_phi_update_kernel(SvgdArgs a)
+{
+    const int64_t p = blockIdx.y;
+    const int K = a.K;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int k = blockIdx.x * 4 + uniform(threadIdx.x >> 6);
+    if (k >= K) return;
+    const PairDesc pd = a.pairs[p];
+    const double* __restrict__ th = a.theta + p * K * 6;
+    const double* __restrict__ gb = a.gbar + p * K * 6;
+    const double ht = a.h[2 * p], hr = a.h[2 * p + 1];
+    const double ct = -(2.0 / ht), cr = -(2.0 / hr);
+    const double N = (double)pd.n_scale;
+    double tk[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) tk[d] = th[6 * k + d];
+
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int l = lane; l < K; l += kWave) {
+        double tl[6], G[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) tl[d] = th[6 * l + d];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            double pg = 0.0;
+            if (a.prm.prior == 1) {
+                const double y = tl[d] - a.prm.prior_mu[d];
+                pg = d < 3 ? -y / a.prm.prior_var[d] : -a.prm.prior_kappa[d - 3] * sin(y);
+            }
+            G[d] = -N * gb[6 * l + d] + pg;
         }
-    } else {
-        const double bc1 = 1.0 - pow(a.prm.beta1, (double)t_new);
-        const double bc2 = 1.0 - pow(a.prm.beta2, (double)t_new);
-        double* __restrict__ mo = a.mom + p * K * 6;
-        double* __restrict__ ve = a.vel + p * K * 6;
-        for (int e = tid; e < 6 * K; e += kSvgdThreads) {
+        double kt = 1.0, kr = 1.0;
+        if (l != k) {
+            kt = exp(-dist2_trans(tl, tk) / ht);
+            kr = exp(-dist2_rot(tl, tk) / hr);
+        }
+        {
 #pragma clang fp contract(off)
-            const double g = -ph[e];
-            const double mm = a.prm.beta1 * mo[e] + (1.0 - a.prm.beta1) * g;
-            const double vv = a.prm.beta2 * ve[e] + (1.0 - a.prm.beta2) * (g * g);
-            mo[e] = mm;
-            ve[e] = vv;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                acc[d] += G[d] * kt + ct * (tl[d] - tk[d]) * kt;
+                acc[3 + d] += G[3 + d] * kr + cr * wrap_pi(tl[3 + d] - tk[3 + d]) * kr;
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        double x = acc[d];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        acc[d] = x;
+    }
+    // lanes 0..5 update one component each
+    double phi_d = 0.0, tnew = 0.0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+        if (lane == d) phi_d = acc[d] / K;
+    const int64_t e = (p * K + k) * 6 + lane;
+    if (lane < 6) {
+#pragma clang fp contract(off)
+        a.phi[e] = phi_d;
+        if (a.prm.optimizer == 1) {
+            tnew = th[6 * k + lane] + a.prm.lr * phi_d;
+        } else {
+            const double t_new = (double)(a.step[p] + 1);
+            const double bc1 = 1.0 - pow(a.prm.beta1, t_new);
+            const double bc2 = 1.0 - pow(a.prm.beta2, t_new);
+            const double g = -phi_d;
+            const double mm = a.prm.beta1 * a.mom[e] + (1.0 - a.prm.beta1) * g;
+            const double vv = a.prm.beta2 * a.vel[e] + (1.0 - a.prm.beta2) * (g * g);
+            a.mom[e] = mm;
+            a.vel[e] = vv;
             const double mhat = mm / bc1;
             const double vhat = vv / bc2;
-            th[e] = th[e] - a.prm.lr * mhat / (sqrt(vhat) + a.prm.eps);
+            tnew = th[6 * k + lane] - a.prm.lr * mhat / (sqrt(vhat) + a.prm.eps);
         }
+        a.theta_next[e] = tnew;
     }
-    __threadfence_block();
-    __syncthreads();
-    for (int k = tid; k < K; k += kSvgdThreads) pose_from_theta(th + 6 * k, a.pose + p * K + k);
-    if (tid == 0) a.step[p] = t_new;
+    double tn[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) tn[d] = __shfl(tnew, d);
+    if (lane == 0) pose_from_theta(tn, a.pose + p * K + k);
+}
+
+// grid pairs: commit the new particles and advance the step count.
+__global__ void svgd_finish_kernel(SvgdArgs a)
+{
+    const int64_t p = blockIdx.x;
+    for (int e = threadIdx.x; e < 6 * a.K; e += blockDim.x)
+        a.theta[p * a.K * 6 + e] = a.theta_next[p * a.K * 6 + e];
+    if (threadIdx.x == 0) a.step[p] += 1;
 }
 
 }  // namespace sicp

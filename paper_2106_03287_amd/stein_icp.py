@@ -265,11 +265,11 @@ def stein_icp_nn_tiling(ctx):
 
 
 def stein_icp_stage_times(ctx, n_iters, stream=None):
-    """Summed ms per stage (nn, grad, svgd+update) over n_iters profiled iterations."""
-    out = (C.c_double * 3)()
+    """Summed ms per stage over n_iters profiled iterations."""
+    out = (C.c_double * 4)()
     _check("stein_icp_stage_times", lib().stein_icp_stage_times(ctx, int(n_iters), out,
                                                                 _stream(stream)))
-    return {"nn": out[0], "grad": out[1], "svgd_update": out[2]}
+    return {"nn": out[0], "grad": out[1], "bandwidth": out[2], "phi_update": out[3]}
 
 
 def stein_icp_destroy(ctx):

@@ -294,3 +294,36 @@ def test_invalid_device_inputs_are_rejected():
     big[0, 0] = 3e9
     with pytest.raises(S.SteinICPError):
         S.stein_icp_nn(dev(prob.pair.src), dev(big))
+
+
+# ------------------------------------------------------------------ median selection paths
+
+def _theta_variant(prob, kind, rng):
+    K = prob.K
+    th = prob.theta0.copy()
+    if kind == "identical":
+        th[:] = th[0]
+    elif kind == "two_clusters":
+        th[: K // 2] = th[0]
+        th[K // 2:] = th[1]
+    elif kind == "near_duplicates":
+        th = th[0] + rng.normal(scale=1e-9, size=th.shape)
+    elif kind == "few_values":
+        th = th[rng.integers(0, 5, K)]
+    return th
+
+
+@pytest.mark.parametrize("kind", ["identical", "two_clusters", "near_duplicates", "few_values"])
+def test_bandwidth_selection_degenerate_particle_sets(kind):
+    prob = synth.make_problem("cuboid", 13, K=120, T=2)
+    prob.theta0 = _theta_variant(prob, kind, np.random.default_rng(5))
+    print(f"selection case {kind}", flush=True)
+    _one_step_compare(prob)
+
+
+@pytest.mark.parametrize("K", [346, 347, 400])
+def test_bandwidth_keyed_and_global_paths(K):
+    prob = synth.make_problem("cuboid", 14, K=K, m=8, T=2)
+    print(f"K={K}", flush=True)
+    _one_step_compare(prob)
+    assert_poses_close(gpu_run(prob, prob.T), oracle_run(prob, prob.T))
