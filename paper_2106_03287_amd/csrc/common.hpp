@@ -24,6 +24,8 @@ struct PairDesc {
     int64_t sched_off;  // into the int32 schedule (rows x m)
     int64_t part_off;   // into the uint64 partial-argmin buffer (chunks x K*m)
     int64_t n_scale;    // N in "N gbar"
+    int64_t q_off;      // into the float4 query buffer
+    int64_t nq;         // queries of this pair (K * m in a solver context)
     int32_t chunks;     // reference chunks, one partial argmin each
     int32_t chunk;      // references per chunk (multiple of 4 * kTile)
     int32_t qblocks;    // query blocks of kWave * Q queries

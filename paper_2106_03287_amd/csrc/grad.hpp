@@ -2,14 +2,16 @@
 // reduction of the per-chunk nearest-neighbour keys.
 //
 // One workgroup per particle. Each thread takes minibatch points i = tid,
-// tid + 256, ...: it reduces the chunk keys of its query to the matched
-// reference index, recomputes the FP64 transform s' = R s + u, forms the
+// tid + 256, ...: it reduces the chunk keys of its query and resolves the
+// winning tile to the matched reference index, recomputes the FP64
+// transform s' = R s + u, forms the
 // residual e = s' - r and the six contributions e and e^T (dR/dtheta_d) s,
 // accumulating in FP64. The 256 partial sums are combined by a fixed-shape
 // tree in LDS, so the result does not depend on scheduling.
 #pragma once
 
 #include "common.hpp"
+#include "nn.hpp"
 
 namespace sicp {
 
@@ -17,6 +19,7 @@ struct GradArgs {
     const PairDesc* pairs;
     const float4* src4;
     const float4* ref4;
+    const float4* queries;
     const int32_t* sched;
     const Pose* pose;
     const int64_t* step;
@@ -39,17 +42,8 @@ __global__ __launch_bounds__(kGradThreads) void grad_kernel(GradArgs a)
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < a.m; i += kGradThreads) {
         const int64_t qi = k * a.m + i;
-        // chunk keys, eight loads in flight at a time
-        uint64_t key = ~0ull;
-        const uint64_t* __restrict__ kp = a.partial + pd.part_off + qi;
-        for (int c0 = 0; c0 < pd.chunks; c0 += 8) {
-            uint64_t kk[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) kk[u] = c0 + u < pd.chunks ? kp[(int64_t)(c0 + u) * nq] : ~0ull;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) key = min(key, kk[u]);
-        }
-        const int32_t j = (int32_t)(uint32_t)(key & 0xffffffffull);
+        const uint64_t key = min_chunk_keys(a.partial + pd.part_off + qi, pd.chunks, nq);
+        const int32_t j = resolve_key(key, a.queries[pd.q_off + qi], a.ref4 + pd.ref_off, pd.n_ref_pad);
         a.match[p * nq + qi] = j;
         const float4 s = a.src4[pd.src_off + a.sched[pd.sched_off + row * a.m + i]];
         const float4 r = a.ref4[pd.ref_off + j];

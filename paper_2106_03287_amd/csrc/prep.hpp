@@ -14,6 +14,7 @@ namespace sicp {
 //   dR/dyaw  = rows (-R row1, R row0, 0)
 __device__ inline void pose_from_theta(const double* __restrict__ th, Pose* __restrict__ P)
 {
+#pragma clang fp contract(off)
     double sr, cr, sp, cp, sy, cy;
     sincos(th[3], &sr, &cr);
     sincos(th[4], &sp, &cp);
@@ -52,6 +53,32 @@ __global__ void pose_kernel(const double* __restrict__ theta, Pose* __restrict__
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) pose_from_theta(theta + 6 * k, pose + k);
+}
+
+// FP32 queries of one iteration: query k * m + i of a pair is the FP64
+// transform of minibatch point i by particle k's pose, rounded once.
+__device__ __forceinline__ float4 make_query(const Pose* __restrict__ P, float4 s)
+{
+    double q[3];
+    transform_f64(P->R, P->u, s.x, s.y, s.z, q);
+    return make_float4((float)q[0], (float)q[1], (float)q[2], 0.0f);
+}
+
+// grid (ceil(K m / 256), pairs): queries of the iteration whose step count
+// is step[p] (schedule row step mod rows).
+__global__ void queries_kernel(const PairDesc* __restrict__ pairs, const float4* __restrict__ src4,
+                               const int32_t* __restrict__ sched, const Pose* __restrict__ pose,
+                               const int64_t* __restrict__ step, float4* __restrict__ queries, int32_t K,
+                               int32_t m, int32_t rows)
+{
+    const int64_t p = blockIdx.y;
+    const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const PairDesc pd = pairs[p];
+    if (qi >= pd.nq) return;
+    const int64_t k = qi / m, i = qi - k * m;
+    const int64_t row = step[p] % rows;
+    const float4 sp = src4[pd.src_off + sched[pd.sched_off + row * m + i]];
+    queries[pd.q_off + qi] = make_query(pose + p * K + k, sp);
 }
 
 __device__ inline bool coord_ok(float v) { return isfinite(v) && fabsf(v) <= 1e9f; }

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -87,12 +88,12 @@ void make_init(uint64_t seed, int32_t K, double ht, double hr, const double* cen
 // ------------------------------------------------------------------ tiling
 struct Tiling {
     int q = 2;                   // queries per lane
+    int w = 4;                   // wavefronts per workgroup
     std::vector<int32_t> chunk;  // per pair, references per chunk
 };
 
 // Default shape: enough workgroups to give every SIMD several waves, with at
-// least 256 references (16 tiles) per wave so the fixed per-wave work (query
-// transform, index recovery, merge) stays small.
+// least 64 references (4 tiles) per wave; the autotuner refines it.
 Tiling default_tiling(const std::vector<PairDesc>& pd, int64_t nq)
 {
     Tiling t;
@@ -101,12 +102,24 @@ Tiling default_tiling(const std::vector<PairDesc>& pd, int64_t nq)
     const int64_t target_wg = 4096;  // x4 waves = 16k waves over 1024 SIMDs
     const int64_t per_pair = std::max<int64_t>(1, ceil_div(target_wg, (int64_t)pd.size() * qb));
     for (const auto& p : pd) {
-        const int64_t max_chunks = std::max<int64_t>(1, p.n_ref_pad / (4 * 256));
+        const int64_t max_chunks = std::max<int64_t>(1, p.n_ref_pad / (4 * 64));
         const int64_t c = std::min(per_pair, max_chunks);
         t.chunk.push_back((int32_t)round_up(ceil_div(p.n_ref_pad, c), 4 * kTile));
     }
     return t;
 }
+
+// Tuned shapes by (pairs, queries per pair, total padded references),
+// shared by every context of the process.
+struct TuneKey {
+    int32_t P;
+    int64_t nq, refs;
+    bool operator<(const TuneKey& o) const
+    {
+        return P != o.P ? P < o.P : (nq != o.nq ? nq < o.nq : refs < o.refs);
+    }
+};
+std::map<TuneKey, std::pair<Tiling, double>> g_tuned;
 
 }  // namespace
 
@@ -130,6 +143,7 @@ struct stein_icp_ctx {
     double* h = nullptr;
     int64_t* step = nullptr;
     Pose* pose = nullptr;
+    float4* queries = nullptr;   // FP32 queries of the coming iteration, K*m per pair
     int32_t* match = nullptr;
     double* dscr = nullptr;
     int* flag = nullptr;
@@ -217,15 +231,25 @@ constexpr int64_t kMaxRef = ((int64_t)1 << 31) - 64;
 
 dim3 grid1d(int64_t n, int threads) { return dim3((unsigned)ceil_div(std::max<int64_t>(n, 1), threads)); }
 
-// Launch the NN kernel for the context's queries (FROM_POSE) or direct queries.
-template <bool FROM_POSE>
-hipError_t launch_nn(int q, unsigned nwork, const NNArgs& a, hipStream_t s)
+// Launch the NN kernel with q queries per lane and w wavefronts per workgroup.
+template <int Q>
+void launch_nn_q(int w, unsigned nwork, const NNArgs& a, hipStream_t s)
+{
+    switch (w) {
+    case 4: hipLaunchKernelGGL((nn_fp32_kernel<Q, 4>), dim3(nwork), dim3(kWave * 4), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((nn_fp32_kernel<Q, 8>), dim3(nwork), dim3(kWave * 8), 0, s, a); break;
+    default: hipLaunchKernelGGL((nn_fp32_kernel<Q, 16>), dim3(nwork), dim3(kWave * 16), 0, s, a); break;
+    }
+}
+
+hipError_t launch_nn(const Tiling& t, unsigned nwork, const NNArgs& a, hipStream_t s)
 {
     if (nwork == 0) return hipSuccess;
-    switch (q) {
-    case 1: hipLaunchKernelGGL((nn_fp32_kernel<1, FROM_POSE>), dim3(nwork), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((nn_fp32_kernel<2, FROM_POSE>), dim3(nwork), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((nn_fp32_kernel<4, FROM_POSE>), dim3(nwork), dim3(256), 0, s, a); break;
+    if (t.w != 4 && t.w != 8 && t.w != 16) return hipErrorInvalidValue;
+    switch (t.q) {
+    case 1: launch_nn_q<1>(t.w, nwork, a, s); break;
+    case 2: launch_nn_q<2>(t.w, nwork, a, s); break;
+    case 4: launch_nn_q<4>(t.w, nwork, a, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -286,16 +310,9 @@ NNArgs nn_args(const stein_icp_ctx* c)
     NNArgs a{};
     a.work = c->d_work;
     a.pairs = c->d_pairs;
-    a.src4 = c->src4;
     a.ref4 = c->ref4;
-    a.sched = c->sched;
-    a.pose = c->pose;
-    a.step = c->step;
-    a.queries = nullptr;
+    a.queries = c->queries;
     a.partial = c->partial;
-    a.K = c->K;
-    a.m = c->m;
-    a.rows = c->rows;
     return a;
 }
 
@@ -313,21 +330,35 @@ SvgdArgs svgd_args(const stein_icp_ctx* c)
     v.h = c->h;
     v.dscr = c->dscr;
     v.pose = c->pose;
+    v.src4 = c->src4;
+    v.sched = c->sched;
+    v.queries = c->queries;
     v.K = c->K;
+    v.m = c->m;
+    v.rows = c->rows;
     v.prm = svgd_params(c->cfg);
     return v;
+}
+
+// Queries of the coming iteration from the current poses and step count.
+hipError_t enqueue_queries(const stein_icp_ctx* c, hipStream_t s)
+{
+    hipLaunchKernelGGL(queries_kernel, dim3((unsigned)ceil_div(c->nq, 256), (unsigned)c->P), dim3(256), 0, s,
+                       c->d_pairs, c->src4, c->sched, c->pose, c->step, c->queries, c->K, c->m, c->rows);
+    return hipGetLastError();
 }
 
 // Stage 0: nearest neighbours, 1: gradients, 2: bandwidths, 3: Stein
 // direction, update and commit.
 hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
 {
-    if (stage == 0) return launch_nn<true>(c->tiling.q, (unsigned)c->work.size(), nn_args(c), s);
+    if (stage == 0) return launch_nn(c->tiling, (unsigned)c->work.size(), nn_args(c), s);
     if (stage == 1) {
     GradArgs g{};
     g.pairs = c->d_pairs;
     g.src4 = c->src4;
     g.ref4 = c->ref4;
+    g.queries = c->queries;
     g.sched = c->sched;
     g.pose = c->pose;
     g.step = c->step;
@@ -433,52 +464,69 @@ int run_iters(stein_icp_ctx* c, int32_t n, hipStream_t s)
     return STEIN_ICP_OK;
 }
 
-// Autotuner: time candidate tile shapes on the context's own data with the
-// real kernel, keep the fastest. Each candidate changes only the NN work
-// decomposition, never the arithmetic, so results are identical across
-// shapes.
+// Autotuner: time candidate NN shapes (queries per lane, wavefronts per
+// workgroup, references per wavefront) on the context's own data with the
+// real nearest-neighbour and gradient kernels (the chunk count trades NN
+// parallelism against the gradient kernel's reduction over chunks) and keep
+// the fastest. Shapes change only the work decomposition, never the
+// arithmetic, so results are identical for every candidate. Results are
+// cached per (pairs, queries, references) for the process.
 int autotune(stein_icp_ctx* c, hipStream_t s)
 {
-    struct Cand {
-        int q;
-        int64_t per_wave;
-    };
-    std::vector<Cand> cands;
-    for (int q : {1, 2, 4})
-        for (int64_t pw : {256, 512, 1024, 2048, 4096}) cands.push_back({q, pw});
+    int64_t refs = 0;
+    for (const auto& pd : c->pairs) refs += pd.n_ref_pad;
+    const TuneKey tk{c->P, c->nq, refs};
+    auto hit = g_tuned.find(tk);
+    if (hit != g_tuned.end()) {
+        c->tiling = hit->second.first;
+        c->tuned_ms = hit->second.second;
+        return upload_tiling(c, s);
+    }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     double best = 1e30;
     Tiling best_t = c->tiling;
-    for (const Cand& cd : cands) {
-        Tiling t;
-        t.q = cd.q;
-        for (const auto& pd : c->pairs) {
-            const int64_t chunks = std::max<int64_t>(1, ceil_div(pd.n_ref_pad, 4 * cd.per_wave));
-            t.chunk.push_back((int32_t)round_up(ceil_div(pd.n_ref_pad, chunks), 4 * kTile));
-        }
-        c->tiling = t;
-        int rc = upload_tiling(c, s);
-        if (rc) return rc;
-        const NNArgs a = nn_args(c);
-        HIP_TRY(launch_nn<true>(t.q, (unsigned)c->work.size(), a, s));  // warm-up
-        const int reps = 5;
-        HIP_TRY(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) HIP_TRY(launch_nn<true>(t.q, (unsigned)c->work.size(), a, s));
-        HIP_TRY(hipEventRecord(e1, s));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (ms / reps < best) {
-            best = ms / reps;
-            best_t = t;
-        }
-    }
+    std::set<std::vector<int32_t>> seen;
+    for (int q : {1, 2, 4})
+        for (int w : {4, 8, 16})
+            for (int64_t pw : {64, 128, 256, 512, 1024, 2048, 4096}) {
+                Tiling t;
+                t.q = q;
+                t.w = w;
+                for (const auto& pd : c->pairs) {
+                    const int64_t chunks = std::max<int64_t>(1, ceil_div(pd.n_ref_pad, (int64_t)w * pw));
+                    t.chunk.push_back((int32_t)round_up(ceil_div(pd.n_ref_pad, chunks), (int64_t)w * kTile));
+                }
+                std::vector<int32_t> sig = t.chunk;
+                sig.push_back(q);
+                sig.push_back(w);
+                if (!seen.insert(sig).second) continue;   // same shape as an earlier span
+                c->tiling = t;
+                int rc = upload_tiling(c, s);
+                if (rc) return rc;
+                HIP_TRY(enqueue_stage(c, 0, s));  // warm-up
+                HIP_TRY(enqueue_stage(c, 1, s));
+                const int reps = 5;
+                HIP_TRY(hipEventRecord(e0, s));
+                for (int r = 0; r < reps; ++r) {
+                    HIP_TRY(enqueue_stage(c, 0, s));
+                    HIP_TRY(enqueue_stage(c, 1, s));
+                }
+                HIP_TRY(hipEventRecord(e1, s));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (ms / reps < best) {
+                    best = ms / reps;
+                    best_t = t;
+                }
+            }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->tiling = best_t;
     c->tuned_ms = best;
+    g_tuned[tk] = {best_t, best};
     return upload_tiling(c, s);
 }
 
@@ -541,6 +589,8 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
         pd.n_ref_pad = round_up(n_ref[p], kTile);
         pd.sched_off = (int64_t)p * rows * m;
         pd.n_scale = cfg->n_scale > 0 ? cfg->n_scale : n_src[p];
+        pd.q_off = (int64_t)p * nq;
+        pd.nq = nq;
         so += pd.n_src;
         ro += pd.n_ref_pad;
         c->pairs.push_back(pd);
@@ -565,6 +615,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     const size_t o_h = take(8 * 2 * (size_t)P);
     const size_t o_step = take(8 * (size_t)P);
     const size_t o_pose = take(sizeof(Pose) * (size_t)P * K);
+    const size_t o_queries = take(sizeof(float4) * (size_t)P * nq);
     const size_t o_match = take(4 * (size_t)P * nq);
     const size_t o_dscr = take(8 * (size_t)P * npairs2);
     const size_t o_flag = take(64);
@@ -586,6 +637,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     c->h = (double*)(c->arena + o_h);
     c->step = (int64_t*)(c->arena + o_step);
     c->pose = (Pose*)(c->arena + o_pose);
+    c->queries = (float4*)(c->arena + o_queries);
     c->match = (int32_t*)(c->arena + o_match);
     c->dscr = (double*)(c->arena + o_dscr);
     c->flag = (int*)(c->arena + o_flag);
@@ -628,6 +680,9 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     }
     hipLaunchKernelGGL(pose_kernel, grid1d((int64_t)P * K, 256), dim3(256), 0, s, c->theta, c->pose, (int64_t)P * K);
     if (hipGetLastError() != hipSuccess) return bail(fail(STEIN_ICP_E_DEVICE, "init kernel launch failed"));
+    if (hipMemcpyAsync(c->d_pairs, c->pairs.data(), sizeof(PairDesc) * P, hipMemcpyHostToDevice, s) != hipSuccess)
+        return bail(fail(STEIN_ICP_E_DEVICE, "pair table upload failed"));
+    if (enqueue_queries(c, s) != hipSuccess) return bail(fail(STEIN_ICP_E_DEVICE, "query kernel launch failed"));
     int flag = 0;
     if (hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -749,6 +804,7 @@ int stein_icp_set_state(stein_icp_ctx* ctx, const double* theta, const double* m
     hipLaunchKernelGGL(pose_kernel, grid1d((int64_t)ctx->P * ctx->K, 256), dim3(256), 0, s, ctx->theta, ctx->pose,
                        (int64_t)ctx->P * ctx->K);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(enqueue_queries(ctx, s));
     return STEIN_ICP_OK;
 }
 
@@ -834,8 +890,8 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     if (!q_xyz || !ref_xyz || !idx) return fail(STEIN_ICP_E_INVALID, "a pointer is NULL");
     hipStream_t s = (hipStream_t)hip_stream;
     PairDesc pd{};
-    pd.src_off = 0;
-    pd.n_src = nq;
+    pd.q_off = 0;
+    pd.nq = nq;
     pd.n_ref = n_ref;
     pd.n_ref_pad = round_up(n_ref, kTile);
     std::vector<PairDesc> v{pd};
@@ -883,9 +939,10 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess && flag) rc = fail(STEIN_ICP_E_INVALID, "a coordinate is non-finite or above 1e9");
     if (e == hipSuccess && !rc) {
-        e = launch_nn<false>(t.q, (unsigned)work.size(), a, s);
+        e = launch_nn(t, (unsigned)work.size(), a, s);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(nn_finish_kernel, grid1d(nq, 256), dim3(256), 0, s, a.partial, nq, pd.chunks, idx, d2);
+            hipLaunchKernelGGL(nn_finish_kernel, grid1d(nq, 256), dim3(256), 0, s, a.partial, a.queries, a.ref4,
+                               pd.n_ref_pad, nq, pd.chunks, idx, d2);
             e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);

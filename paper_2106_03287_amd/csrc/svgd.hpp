@@ -18,8 +18,8 @@
 //    G_l = -N gbar_l + grad log p(theta_l) (Eq. 10 with Eqs. 14-15), lanes over
 //    l and a fixed-shape shuffle reduction; then Adam on -phi (or
 //    theta += lr phi) for particle k, written to a second buffer (other
-//    wavefronts still read the current particles), and the particle's next
-//    pose.
+//    wavefronts still read the current particles), the particle's next pose
+//    and its FP32 queries of the next iteration.
 //  * svgd_finish_kernel: commits the new particles and advances the step.
 #pragma once
 
@@ -47,9 +47,12 @@ struct SvgdArgs {
     const double* gbar;
     double* phi;
     double* h;            // 2 per pair
-    double* dscr;         // K(K-1)/2 per pair and block, for K above the register limit
+    double* dscr;         // K(K-1)/2 per pair and block, for K above the keyed limit
     Pose* pose;
-    int32_t K, pad_;
+    const float4* src4;
+    const int32_t* sched;
+    float4* queries;      // FP32 queries of the next iteration
+    int32_t K, m, rows, pad_;
     SvgdParams prm;
 };
 
@@ -564,7 +567,24 @@ __global__ __launch_bounds__(256) void svgd_phi_update_kernel(SvgdArgs a)
     double tn[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) tn[d] = __shfl(tnew, d);
-    if (lane == 0) pose_from_theta(tn, a.pose + p * K + k);
+    // the new pose (every lane computes the same bits) and this particle's
+    // queries of the next iteration
+    Pose P;
+    pose_from_theta(tn, &P);
+    if (lane == 0) a.pose[p * K + k] = P;
+    const int64_t row = (a.step[p] + 1) % a.rows;
+    const int32_t* __restrict__ srow = a.sched + pd.sched_off + row * a.m;
+    for (int i0 = lane; i0 < a.m; i0 += 4 * kWave) {
+        int32_t si[4];
+        float4 sp[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) si[u] = i0 + u * kWave < a.m ? srow[i0 + u * kWave] : 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sp[u] = a.src4[pd.src_off + si[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + u * kWave < a.m) a.queries[pd.q_off + (int64_t)k * a.m + i0 + u * kWave] = make_query(&P, sp[u]);
+    }
 }
 
 // grid pairs: commit the new particles and advance the step count.
