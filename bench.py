@@ -35,14 +35,16 @@ def nn_source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, tiling):
     """HBM bytes per NN launch from the committed counter runs, if they were
-    taken on the current kernel source and this workload; else None."""
+    taken on the current kernel source, this workload and this NN shape;
+    else None."""
     path = os.path.join(ROOT, "profiles", "nn_fp32_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(workload)
-    if not rec or rec.get("source_sha") != nn_source_sha():
+    shape = "%d,%d,%d" % (tiling["queries_per_lane"], tiling["waves"], tiling["chunk"])
+    if not rec or rec.get("source_sha") != nn_source_sha() or rec.get("tiling") != shape:
         return None
     return rec["hbm_bytes_per_launch"]
 
@@ -77,6 +79,10 @@ def main():
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
+    ap.add_argument("--iters", type=int, default=0,
+                    help="iterations per solve (default: the workload's T); for short profiled runs")
+    ap.add_argument("--tiling", default="",
+                    help="force the NN shape 'queries_per_lane,waves,chunk' instead of tuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -97,15 +103,19 @@ def main():
         del a, b
 
     prob = synth.make_problem(args.workload, 0)
+    if args.iters:
+        prob.T = args.iters
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     src, ref = dev(prob.pair.src), dev(prob.pair.ref)
     theta0, sched = dev(prob.theta0), dev(prob.schedule)
     cfg = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m,
                                      schedule_rows=prob.schedule.shape[0], lr=prob.lr,
-                                     autotune=args.autotune)
+                                     autotune=0 if args.tiling else args.autotune)
     t_init = time.perf_counter()
     sol = S.SteinICP(cfg, src, ref, theta0, sched)
     init_ms = (time.perf_counter() - t_init) * 1e3
+    if args.tiling:
+        sol.set_tiling(*[int(x) for x in args.tiling.split(",")])
     tiling = sol.tiling()
     zeros = torch.zeros_like(theta0)
 
@@ -126,15 +136,16 @@ def main():
     M = len(prob.pair.ref)
     queries_per_s = prob.K * prob.m * iters_per_s
 
-    # stage times (HIP events on the launch stream), one profiled solve
+    # stage times (HIP events on the launch stream around each stage of one
+    # profiled solve) and the NN kernel alone over back-to-back launches
     S.stein_icp_set_state(sol.ctx, theta0, zeros, zeros, 0)
     stage = sol.stage_times(prob.T)
-    nn_ms = stage["nn"] / prob.T
+    nn_ms = sol.time_nn(max(20, min(200, int(200 / max(stage["nn"] / prob.T, 1e-3)))))
     pairs_per_launch = prob.K * prob.m * M
     achieved = pairs_per_launch * FLOPS_PER_PAIR / (nn_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(prob.name),
+                "traffic": measured_traffic(prob.name, tiling),
                 "kernel": "nn_fp32_kernel", "avg_launch_ms": round(nn_ms, 5),
                 "pair_evals_per_launch": pairs_per_launch}
     sol.close()

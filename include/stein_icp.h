@@ -154,11 +154,20 @@ int stein_icp_get_diagnostics(const stein_icp_ctx *ctx, double *gbar, double *ph
 /* Number of pairs, particles and minibatch size of a context. */
 int stein_icp_shape(const stein_icp_ctx *ctx, int32_t *n_pairs, int32_t *K, int32_t *m);
 
-/* NN tile shape the context uses (queries per lane, reference chunk per
- * workgroup, chunks per pair 0) and its mean NN launch time in ms measured
- * by the autotuner (0 if not tuned). */
-int stein_icp_nn_tiling(const stein_icp_ctx *ctx, int32_t *queries_per_lane, int32_t *chunk,
-                        int32_t *chunks, double *tuned_ms);
+/* Nearest-neighbour work shape of the context: FP32 queries per lane,
+ * wavefronts per workgroup, references per workgroup chunk and chunks (of
+ * pair 0), and the mean time in ms of one NN + gradient launch pair measured
+ * by the autotuner (0 if not tuned). Any of the outputs may be NULL. */
+int stein_icp_nn_tiling(const stein_icp_ctx *ctx, int32_t *queries_per_lane, int32_t *waves,
+                        int32_t *chunk, int32_t *chunks, double *tuned_ms);
+
+/* Force the nearest-neighbour work shape: queries_per_lane in {1, 2, 4},
+ * waves in {4, 8, 16}, chunk a positive multiple of 16 references (capped
+ * at each pair's padded reference count). The shape changes only how the
+ * search is split over workgroups, never its result. Blocking (reallocates
+ * the per-chunk key buffer and synchronises `hip_stream`). */
+int stein_icp_set_nn_tiling(stein_icp_ctx *ctx, int32_t queries_per_lane, int32_t waves,
+                            int32_t chunk, void *hip_stream);
 
 /* Profiled mode: run n_iters >= 1 iterations with plain launches (no graph),
  * recording HIP events on `hip_stream` around each stage, and return the
@@ -168,6 +177,13 @@ int stein_icp_nn_tiling(const stein_icp_ctx *ctx, int32_t *queries_per_lane, int
  * graph overlaps the bandwidths with the first two. Advances the state like
  * stein_icp_step. Blocking. */
 int stein_icp_stage_times(stein_icp_ctx *ctx, int32_t n_iters, double *ms_out, void *hip_stream);
+
+/* Mean duration in ms of the nearest-neighbour kernel (Eq. 1) over
+ * n_launches >= 1 back-to-back launches on the current queries, timed with
+ * HIP events on `hip_stream`. The launches only rewrite the per-chunk keys,
+ * which the next iteration recomputes, so the optimiser state is unchanged.
+ * Blocking. */
+int stein_icp_time_nn(stein_icp_ctx *ctx, int32_t n_launches, double *ms_per_launch, void *hip_stream);
 
 /* Release the context and its device memory. NULL is a no-op. Blocking
  * (synchronises the device before freeing). */

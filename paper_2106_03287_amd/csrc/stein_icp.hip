@@ -830,14 +830,33 @@ int stein_icp_shape(const stein_icp_ctx* ctx, int32_t* n_pairs, int32_t* K, int3
     return STEIN_ICP_OK;
 }
 
-int stein_icp_nn_tiling(const stein_icp_ctx* ctx, int32_t* qpl, int32_t* chunk, int32_t* chunks, double* tuned_ms)
+int stein_icp_nn_tiling(const stein_icp_ctx* ctx, int32_t* qpl, int32_t* waves, int32_t* chunk, int32_t* chunks,
+                        double* tuned_ms)
 {
     if (!ctx) return fail(STEIN_ICP_E_INVALID, "ctx is NULL");
     if (qpl) *qpl = ctx->tiling.q;
+    if (waves) *waves = ctx->tiling.w;
     if (chunk) *chunk = ctx->pairs[0].chunk;
     if (chunks) *chunks = ctx->pairs[0].chunks;
     if (tuned_ms) *tuned_ms = ctx->tuned_ms;
     return STEIN_ICP_OK;
+}
+
+int stein_icp_set_nn_tiling(stein_icp_ctx* ctx, int32_t qpl, int32_t waves, int32_t chunk, void* hip_stream)
+{
+    if (!ctx) return fail(STEIN_ICP_E_INVALID, "ctx is NULL");
+    if (qpl != 1 && qpl != 2 && qpl != 4) return fail(STEIN_ICP_E_INVALID, "queries_per_lane must be 1, 2 or 4");
+    if (waves != 4 && waves != 8 && waves != 16) return fail(STEIN_ICP_E_INVALID, "waves must be 4, 8 or 16");
+    if (chunk < kTile || chunk % kTile != 0) return fail(STEIN_ICP_E_INVALID, "chunk must be a positive multiple of 16");
+    Tiling t;
+    t.q = qpl;
+    t.w = waves;
+    for (const auto& pd : ctx->pairs) t.chunk.push_back((int32_t)std::min<int64_t>(chunk, round_up(pd.n_ref_pad, kTile)));
+    const Tiling old = ctx->tiling;
+    ctx->tiling = t;
+    const int rc = upload_tiling(ctx, (hipStream_t)hip_stream);
+    if (rc) ctx->tiling = old;
+    return rc;
 }
 
 int stein_icp_stage_times(stein_icp_ctx* ctx, int32_t n_iters, double* ms_out, void* hip_stream)
@@ -876,6 +895,28 @@ int stein_icp_stage_times(stein_icp_ctx* ctx, int32_t n_iters, double* ms_out, v
     if (rc == STEIN_ICP_OK)
         for (int k = 0; k < kStages; ++k) ms_out[k] = t[k];
     return rc;
+}
+
+int stein_icp_time_nn(stein_icp_ctx* ctx, int32_t n_launches, double* ms_per_launch, void* hip_stream)
+{
+    if (!ctx || !ms_per_launch) return fail(STEIN_ICP_E_INVALID, "ctx or ms_per_launch is NULL");
+    if (n_launches < 1) return fail(STEIN_ICP_E_INVALID, "n_launches must be >= 1");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hipError_t e = enqueue_stage(ctx, 0, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int32_t i = 0; i < n_launches && e == hipSuccess; ++i) e = enqueue_stage(ctx, 0, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(STEIN_ICP_E_DEVICE, std::string("stein_icp_time_nn: ") + hipGetErrorString(e));
+    *ms_per_launch = (double)ms / n_launches;
+    return STEIN_ICP_OK;
 }
 
 void stein_icp_destroy(stein_icp_ctx* ctx) { free_ctx(ctx); }

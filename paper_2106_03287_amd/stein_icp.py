@@ -57,7 +57,8 @@ class stein_icp_config(C.Structure):
 EXPORTS = [
     "stein_icp_default_config", "stein_icp_init", "stein_icp_batch_init", "stein_icp_step",
     "stein_icp_particles", "stein_icp_get_state", "stein_icp_set_state",
-    "stein_icp_get_diagnostics", "stein_icp_shape", "stein_icp_nn_tiling", "stein_icp_stage_times",
+    "stein_icp_get_diagnostics", "stein_icp_shape", "stein_icp_nn_tiling", "stein_icp_set_nn_tiling",
+    "stein_icp_stage_times", "stein_icp_time_nn",
     "stein_icp_destroy",
     "stein_icp_last_error", "stein_icp_nn", "stein_icp_make_schedule", "stein_icp_make_init",
 ]
@@ -88,8 +89,10 @@ def lib():
     L.stein_icp_get_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp]
     L.stein_icp_shape.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     L.stein_icp_nn_tiling.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
-                                      C.POINTER(dbl)]
+                                      C.POINTER(i32), C.POINTER(dbl)]
+    L.stein_icp_set_nn_tiling.argtypes = [vp, i32, i32, i32, vp]
     L.stein_icp_stage_times.argtypes = [vp, i32, C.POINTER(dbl), vp]
+    L.stein_icp_time_nn.argtypes = [vp, i32, C.POINTER(dbl), vp]
     L.stein_icp_destroy.argtypes = [vp]
     L.stein_icp_destroy.restype = None
     L.stein_icp_last_error.argtypes = []
@@ -257,11 +260,16 @@ def stein_icp_get_diagnostics(ctx, stream=None):
 
 
 def stein_icp_nn_tiling(ctx):
-    q, ch, nch, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
-    _check("stein_icp_nn_tiling", lib().stein_icp_nn_tiling(ctx, C.byref(q), C.byref(ch),
+    q, w, ch, nch, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+    _check("stein_icp_nn_tiling", lib().stein_icp_nn_tiling(ctx, C.byref(q), C.byref(w), C.byref(ch),
                                                             C.byref(nch), C.byref(ms)))
-    return {"queries_per_lane": q.value, "chunk": ch.value, "chunks": nch.value,
+    return {"queries_per_lane": q.value, "waves": w.value, "chunk": ch.value, "chunks": nch.value,
             "tuned_ms": ms.value}
+
+
+def stein_icp_set_nn_tiling(ctx, queries_per_lane, waves, chunk, stream=None):
+    _check("stein_icp_set_nn_tiling", lib().stein_icp_set_nn_tiling(
+        ctx, int(queries_per_lane), int(waves), int(chunk), _stream(stream)))
 
 
 def stein_icp_stage_times(ctx, n_iters, stream=None):
@@ -270,6 +278,14 @@ def stein_icp_stage_times(ctx, n_iters, stream=None):
     _check("stein_icp_stage_times", lib().stein_icp_stage_times(ctx, int(n_iters), out,
                                                                 _stream(stream)))
     return {"nn": out[0], "grad": out[1], "bandwidth": out[2], "phi_update": out[3]}
+
+
+def stein_icp_time_nn(ctx, n_launches, stream=None):
+    """Mean ms of the nearest-neighbour kernel over back-to-back launches."""
+    ms = C.c_double()
+    _check("stein_icp_time_nn", lib().stein_icp_time_nn(ctx, int(n_launches), C.byref(ms),
+                                                        _stream(stream)))
+    return ms.value
 
 
 def stein_icp_destroy(ctx):
@@ -341,8 +357,14 @@ class SteinICP:
     def tiling(self):
         return stein_icp_nn_tiling(self.ctx)
 
+    def set_tiling(self, queries_per_lane, waves, chunk):
+        stein_icp_set_nn_tiling(self.ctx, queries_per_lane, waves, chunk)
+
     def stage_times(self, n_iters):
         return stein_icp_stage_times(self.ctx, n_iters)
+
+    def time_nn(self, n_launches):
+        return stein_icp_time_nn(self.ctx, n_launches)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -327,3 +327,27 @@ def test_bandwidth_keyed_and_global_paths(K):
     print(f"K={K}", flush=True)
     _one_step_compare(prob)
     assert_poses_close(gpu_run(prob, prob.T), oracle_run(prob, prob.T))
+
+
+def test_every_nn_work_shape_gives_identical_results():
+    prob = synth.make_problem("kinect", 2, T=3)
+    ref_sol = gpu_solver(prob)
+    ref_sol.step(prob.T)
+    want = ref_sol.particles().cpu().numpy()
+    want_match = ref_sol.diagnostics()["match"].cpu().numpy()
+    ref_sol.close()
+    for q in (1, 2, 4):
+        for w in (4, 8, 16):
+            for chunk in (w * 16, 1024, 20000):
+                sol = gpu_solver(prob)
+                sol.set_tiling(q, w, chunk)
+                sol.step(prob.T)
+                np.testing.assert_array_equal(sol.particles().cpu().numpy(), want)
+                np.testing.assert_array_equal(sol.diagnostics()["match"].cpu().numpy(), want_match)
+                sol.close()
+    with pytest.raises(S.SteinICPError):
+        sol = gpu_solver(prob)
+        try:
+            sol.set_tiling(3, 4, 64)
+        finally:
+            sol.close()
