@@ -43,7 +43,7 @@ def measured_traffic(workload, tiling):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(workload)
-    shape = "%d,%d,%d" % (tiling["queries_per_lane"], tiling["waves"], tiling["chunk"])
+    shape = "%d,%d,%d,%d" % (tiling["queries_per_lane"], tiling["waves"], tiling["chunk"], tiling["persist"])
     if not rec or rec.get("source_sha") != nn_source_sha() or rec.get("tiling") != shape:
         return None
     return rec["hbm_bytes_per_launch"]
@@ -74,7 +74,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="kinect", choices=["cuboid", "kinect", "lidar"])
+    ap.add_argument("--workload", default="kinect", choices=["cuboid", "kinect", "lidar", "batched"])
+    ap.add_argument("--pairs", type=int, default=64, help="pairs of the batched workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -82,7 +83,7 @@ def main():
     ap.add_argument("--iters", type=int, default=0,
                     help="iterations per solve (default: the workload's T); for short profiled runs")
     ap.add_argument("--tiling", default="",
-                    help="force the NN shape 'queries_per_lane,waves,chunk' instead of tuning")
+                    help="force the NN shape 'queries_per_lane,waves,chunk[,persist]' instead of tuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -92,6 +93,9 @@ def main():
     import torch
     import synth
     from paper_2106_03287_amd import stein_icp as S
+
+    if args.workload == "batched":
+        return run_batched(args)
 
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 4
@@ -177,6 +181,97 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+def run_batched(args):
+    """64 uneven pairs advanced together by one context (one launch per stage
+    for all pairs, captured graph), against the same pairs solved one after
+    another by 64 single-pair contexts on the same stream."""
+    import torch
+    import synth
+    from paper_2106_03287_amd import stein_icp as S
+
+    probs = synth.batched_problems(args.pairs)
+    P, K, m = len(probs), probs[0].K, probs[0].m
+    T = args.iters or probs[0].T
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    srcs = [dev(p.pair.src) for p in probs]
+    refs = [dev(p.pair.ref) for p in probs]
+    scheds = [dev(p.schedule) for p in probs]
+    th0 = dev(np.stack([p.theta0 for p in probs]))
+    cfg = S.stein_icp_default_config(num_particles=K, batch_size=m, schedule_rows=probs[0].schedule.shape[0],
+                                     lr=probs[0].lr, autotune=0 if args.tiling else args.autotune)
+    t_init = time.perf_counter()
+    batch = S.SteinICP.batch(cfg, srcs, refs, th0, scheds)
+    init_ms = (time.perf_counter() - t_init) * 1e3
+    if args.tiling:
+        batch.set_tiling(*[int(x) for x in args.tiling.split(",")])
+    tiling = batch.tiling()
+    zeros = torch.zeros_like(th0)
+    singles = [S.SteinICP(cfg, srcs[i], refs[i], th0[i].contiguous(), scheds[i]) for i in range(P)]
+    z1 = torch.zeros_like(th0[0])
+
+    def solve_batched():
+        S.stein_icp_set_state(batch.ctx, th0, zeros, zeros, 0)
+        batch.step(T)
+
+    def solve_sequential():
+        for i, sol in enumerate(singles):
+            S.stein_icp_set_state(sol.ctx, th0[i], z1, z1, 0)
+            sol.step(T)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    ms_b = timed(solve_batched, args.steps, args.warmup)
+    ms_s = timed(solve_sequential, max(1, args.steps // 2), 1)
+    same = bool(torch.equal(batch.particles(), torch.stack([s.particles()[0] for s in singles])))
+    S.stein_icp_set_state(batch.ctx, th0, zeros, zeros, 0)
+    stage = batch.stage_times(T)
+    nn_ms = batch.time_nn(20)
+    pairs_per_launch = sum(K * m * len(p.pair.ref) for p in probs)
+    achieved = pairs_per_launch * FLOPS_PER_PAIR / (nn_ms * 1e-3) / 1e12
+    value = P * T / (ms_b / 1e3)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "pair-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_b, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched", "pairs": P, "K": K, "m": m, "T": T,
+                   "M_range": [min(len(p.pair.ref) for p in probs), max(len(p.pair.ref) for p in probs)],
+                   "N_range": [min(len(p.pair.src) for p in probs), max(len(p.pair.src) for p in probs)],
+                   "nn": "fp32", "step": "one batched solve of all pairs, T iterations"},
+        "sequential_ms": round(ms_s, 3),
+        "sequential_pair_iters_per_s": round(P * T / (ms_s / 1e3), 2),
+        "speedup_vs_sequential": round(ms_s / ms_b, 3),
+        "batched_equals_sequential_bitwise": same,
+        "stage_ms_per_iter": {k: round(v / T, 5) for k, v in stage.items()},
+        "init_ms": round(init_ms, 2),
+        "nn_tiling": tiling,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": "nn_fp32_kernel", "avg_launch_ms": round(nn_ms, 5),
+                     "pair_evals_per_launch": pairs_per_launch},
+    }
+    for s_ in singles:
+        s_.close()
+    batch.close()
     print(json.dumps(out), flush=True)
 
 

@@ -156,18 +156,21 @@ int stein_icp_shape(const stein_icp_ctx *ctx, int32_t *n_pairs, int32_t *K, int3
 
 /* Nearest-neighbour work shape of the context: FP32 queries per lane,
  * wavefronts per workgroup, references per workgroup chunk and chunks (of
- * pair 0), and the mean time in ms of one NN + gradient launch pair measured
- * by the autotuner (0 if not tuned). Any of the outputs may be NULL. */
+ * pair 0), persistence (0: one workgroup per work item; n: n workgroups per
+ * compute unit walking the work table of all pairs), and the mean time in ms
+ * of one NN + gradient launch pair measured by the autotuner (0 if not
+ * tuned). Any of the outputs may be NULL. */
 int stein_icp_nn_tiling(const stein_icp_ctx *ctx, int32_t *queries_per_lane, int32_t *waves,
-                        int32_t *chunk, int32_t *chunks, double *tuned_ms);
+                        int32_t *chunk, int32_t *chunks, int32_t *persist, double *tuned_ms);
 
 /* Force the nearest-neighbour work shape: queries_per_lane in {1, 2, 4},
  * waves in {4, 8, 16}, chunk a positive multiple of 16 references (capped
- * at each pair's padded reference count). The shape changes only how the
- * search is split over workgroups, never its result. Blocking (reallocates
- * the per-chunk key buffer and synchronises `hip_stream`). */
+ * at each pair's padded reference count), persist in [0, 64] as above. The
+ * shape changes only how the search is split over workgroups, never its
+ * result. Blocking (reallocates the per-chunk key buffer and synchronises
+ * `hip_stream`). */
 int stein_icp_set_nn_tiling(stein_icp_ctx *ctx, int32_t queries_per_lane, int32_t waves,
-                            int32_t chunk, void *hip_stream);
+                            int32_t chunk, int32_t persist, void *hip_stream);
 
 /* Profiled mode: run n_iters >= 1 iterations with plain launches (no graph),
  * recording HIP events on `hip_stream` around each stage, and return the

@@ -25,12 +25,13 @@ struct NNArgs {
     const float4* ref4;
     const float4* queries;    // FP32 queries, pair p at pairs[p].q_off, pairs[p].nq of them
     uint64_t* partial;
+    int64_t nwork;
 };
 
+// One work item: queries of a block against one reference chunk.
 template <int Q, int W>
-__global__ __launch_bounds__(kWave * W) void nn_fp32_kernel(NNArgs a)
+__device__ __forceinline__ void nn_item(const NNArgs& a, const WorkItem w, uint64_t (*sk)[kWave * Q])
 {
-    const WorkItem w = a.work[blockIdx.x];
     const PairDesc pd = a.pairs[w.pair];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x >> 6);
@@ -93,7 +94,6 @@ __global__ __launch_bounds__(kWave * W) void nn_fp32_kernel(NNArgs a)
     for (int s = 0; s < Q; ++s)
         key[s] = (t0 < t1) ? pack_key(best[s], (uint32_t)(c0 / kTile + btile[s])) : ~0ull;
 
-    __shared__ uint64_t sk[W][kWave * Q];
 #pragma unroll
     for (int s = 0; s < Q; ++s) sk[wave][s * kWave + lane] = key[s];
     __syncthreads();
@@ -106,6 +106,17 @@ __global__ __launch_bounds__(kWave * W) void nn_fp32_kernel(NNArgs a)
             a.partial[pd.part_off + (int64_t)w.chunk * nq + qi] = k0;
         }
     }
+    __syncthreads();   // sk is reused by the next item of a persistent workgroup
+}
+
+// grid = nwork: one item per workgroup; a smaller grid makes the workgroups
+// persistent, each walking the work table with a grid stride (the table is
+// built so items have near-equal cost, which balances a static stride).
+template <int Q, int W>
+__global__ __launch_bounds__(kWave * W) void nn_fp32_kernel(NNArgs a)
+{
+    __shared__ uint64_t sk[W][kWave * Q];
+    for (int64_t it = blockIdx.x; it < a.nwork; it += gridDim.x) nn_item<Q, W>(a, a.work[it], sk);
 }
 
 // Smallest of `chunks` keys strided by `stride`, eight loads in flight.

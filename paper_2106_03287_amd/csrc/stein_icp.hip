@@ -89,6 +89,7 @@ void make_init(uint64_t seed, int32_t K, double ht, double hr, const double* cen
 struct Tiling {
     int q = 2;                   // queries per lane
     int w = 4;                   // wavefronts per workgroup
+    int persist = 0;             // 0: one workgroup per item; n: n workgroups per CU, grid-stride
     std::vector<int32_t> chunk;  // per pair, references per chunk
 };
 
@@ -242,14 +243,18 @@ void launch_nn_q(int w, unsigned nwork, const NNArgs& a, hipStream_t s)
     }
 }
 
-hipError_t launch_nn(const Tiling& t, unsigned nwork, const NNArgs& a, hipStream_t s)
+int g_num_cus = 256;
+
+hipError_t launch_nn(const Tiling& t, unsigned nwork, NNArgs a, hipStream_t s)
 {
     if (nwork == 0) return hipSuccess;
     if (t.w != 4 && t.w != 8 && t.w != 16) return hipErrorInvalidValue;
+    a.nwork = nwork;
+    const unsigned grid = t.persist > 0 ? std::min<unsigned>(nwork, (unsigned)(t.persist * g_num_cus)) : nwork;
     switch (t.q) {
-    case 1: launch_nn_q<1>(t.w, nwork, a, s); break;
-    case 2: launch_nn_q<2>(t.w, nwork, a, s); break;
-    case 4: launch_nn_q<4>(t.w, nwork, a, s); break;
+    case 1: launch_nn_q<1>(t.w, grid, a, s); break;
+    case 2: launch_nn_q<2>(t.w, grid, a, s); break;
+    case 4: launch_nn_q<4>(t.w, grid, a, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -522,6 +527,30 @@ int autotune(stein_icp_ctx* c, hipStream_t s)
                     best_t = t;
                 }
             }
+    // persistent grids on the best shape
+    for (int per : {1, 2, 4, 8}) {
+        Tiling t = best_t;
+        t.persist = per;
+        c->tiling = t;
+        int rc = upload_tiling(c, s);
+        if (rc) return rc;
+        HIP_TRY(enqueue_stage(c, 0, s));
+        HIP_TRY(enqueue_stage(c, 1, s));
+        const int reps = 5;
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) {
+            HIP_TRY(enqueue_stage(c, 0, s));
+            HIP_TRY(enqueue_stage(c, 1, s));
+        }
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms / reps < best) {
+            best = ms / reps;
+            best_t = t;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->tiling = best_t;
@@ -569,6 +598,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
 
     int device = 0;
     HIP_TRY(hipGetDevice(&device));
+    HIP_TRY(hipDeviceGetAttribute(&g_num_cus, hipDeviceAttributeMultiprocessorCount, device));
     auto* c = new stein_icp_ctx();
     c->device = device;
     c->cfg = *cfg;
@@ -831,10 +861,11 @@ int stein_icp_shape(const stein_icp_ctx* ctx, int32_t* n_pairs, int32_t* K, int3
 }
 
 int stein_icp_nn_tiling(const stein_icp_ctx* ctx, int32_t* qpl, int32_t* waves, int32_t* chunk, int32_t* chunks,
-                        double* tuned_ms)
+                        int32_t* persist, double* tuned_ms)
 {
     if (!ctx) return fail(STEIN_ICP_E_INVALID, "ctx is NULL");
     if (qpl) *qpl = ctx->tiling.q;
+    if (persist) *persist = ctx->tiling.persist;
     if (waves) *waves = ctx->tiling.w;
     if (chunk) *chunk = ctx->pairs[0].chunk;
     if (chunks) *chunks = ctx->pairs[0].chunks;
@@ -842,15 +873,18 @@ int stein_icp_nn_tiling(const stein_icp_ctx* ctx, int32_t* qpl, int32_t* waves, 
     return STEIN_ICP_OK;
 }
 
-int stein_icp_set_nn_tiling(stein_icp_ctx* ctx, int32_t qpl, int32_t waves, int32_t chunk, void* hip_stream)
+int stein_icp_set_nn_tiling(stein_icp_ctx* ctx, int32_t qpl, int32_t waves, int32_t chunk, int32_t persist,
+                            void* hip_stream)
 {
     if (!ctx) return fail(STEIN_ICP_E_INVALID, "ctx is NULL");
+    if (persist < 0 || persist > 64) return fail(STEIN_ICP_E_INVALID, "persist must be in [0, 64]");
     if (qpl != 1 && qpl != 2 && qpl != 4) return fail(STEIN_ICP_E_INVALID, "queries_per_lane must be 1, 2 or 4");
     if (waves != 4 && waves != 8 && waves != 16) return fail(STEIN_ICP_E_INVALID, "waves must be 4, 8 or 16");
     if (chunk < kTile || chunk % kTile != 0) return fail(STEIN_ICP_E_INVALID, "chunk must be a positive multiple of 16");
     Tiling t;
     t.q = qpl;
     t.w = waves;
+    t.persist = persist;
     for (const auto& pd : ctx->pairs) t.chunk.push_back((int32_t)std::min<int64_t>(chunk, round_up(pd.n_ref_pad, kTile)));
     const Tiling old = ctx->tiling;
     ctx->tiling = t;

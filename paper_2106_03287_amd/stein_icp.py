@@ -89,8 +89,8 @@ def lib():
     L.stein_icp_get_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp]
     L.stein_icp_shape.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     L.stein_icp_nn_tiling.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
-                                      C.POINTER(i32), C.POINTER(dbl)]
-    L.stein_icp_set_nn_tiling.argtypes = [vp, i32, i32, i32, vp]
+                                      C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl)]
+    L.stein_icp_set_nn_tiling.argtypes = [vp, i32, i32, i32, i32, vp]
     L.stein_icp_stage_times.argtypes = [vp, i32, C.POINTER(dbl), vp]
     L.stein_icp_time_nn.argtypes = [vp, i32, C.POINTER(dbl), vp]
     L.stein_icp_destroy.argtypes = [vp]
@@ -260,16 +260,17 @@ def stein_icp_get_diagnostics(ctx, stream=None):
 
 
 def stein_icp_nn_tiling(ctx):
-    q, w, ch, nch, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+    q, w, ch, nch, per = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    ms = C.c_double()
     _check("stein_icp_nn_tiling", lib().stein_icp_nn_tiling(ctx, C.byref(q), C.byref(w), C.byref(ch),
-                                                            C.byref(nch), C.byref(ms)))
+                                                            C.byref(nch), C.byref(per), C.byref(ms)))
     return {"queries_per_lane": q.value, "waves": w.value, "chunk": ch.value, "chunks": nch.value,
-            "tuned_ms": ms.value}
+            "persist": per.value, "tuned_ms": ms.value}
 
 
-def stein_icp_set_nn_tiling(ctx, queries_per_lane, waves, chunk, stream=None):
+def stein_icp_set_nn_tiling(ctx, queries_per_lane, waves, chunk, persist=0, stream=None):
     _check("stein_icp_set_nn_tiling", lib().stein_icp_set_nn_tiling(
-        ctx, int(queries_per_lane), int(waves), int(chunk), _stream(stream)))
+        ctx, int(queries_per_lane), int(waves), int(chunk), int(persist), _stream(stream)))
 
 
 def stein_icp_stage_times(ctx, n_iters, stream=None):
@@ -357,8 +358,8 @@ class SteinICP:
     def tiling(self):
         return stein_icp_nn_tiling(self.ctx)
 
-    def set_tiling(self, queries_per_lane, waves, chunk):
-        stein_icp_set_nn_tiling(self.ctx, queries_per_lane, waves, chunk)
+    def set_tiling(self, queries_per_lane, waves, chunk, persist=0):
+        stein_icp_set_nn_tiling(self.ctx, queries_per_lane, waves, chunk, persist)
 
     def stage_times(self, n_iters):
         return stein_icp_stage_times(self.ctx, n_iters)

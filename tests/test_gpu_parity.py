@@ -351,3 +351,28 @@ def test_every_nn_work_shape_gives_identical_results():
             sol.set_tiling(3, 4, 64)
         finally:
             sol.close()
+
+
+def test_batched_uneven_pairs_tuned_and_persistent():
+    probs = synth.batched_problems(6, K=16, m=40, T=5, size_scale=0.2)
+    gcfg, _ = both_configs(probs[0])
+    srcs = [dev(p.pair.src) for p in probs]
+    refs = [dev(p.pair.ref) for p in probs]
+    th0 = dev(np.stack([p.theta0 for p in probs]))
+    scheds = [dev(p.schedule) for p in probs]
+    outs = []
+    for tiling in (None, "tuned", (2, 8, 512, 2), (1, 16, 64, 1)):
+        cfg = S.stein_icp_default_config(num_particles=16, batch_size=40, schedule_rows=5, lr=probs[0].lr,
+                                         autotune=1 if tiling == "tuned" else 0)
+        b = S.SteinICP.batch(cfg, srcs, refs, th0, scheds)
+        if isinstance(tiling, tuple):
+            b.set_tiling(*tiling)
+        b.step(5)
+        outs.append(b.particles().cpu().numpy())
+        b.close()
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    for i, p in enumerate(probs):
+        np.testing.assert_array_equal(outs[0][i], gpu_run(p, 5))
+        if i < 2:
+            assert_poses_close(outs[0][i], oracle_run(p, 5))
