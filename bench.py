@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Stein-ICP iters/s & particle·point NN queries/s; time-to-MMD≤0.05 vs plain"
 VALU_PEAK_TFLOPS = 157.3    # MI355X FP32 vector peak: 256 CUs x 2.4 GHz x 256 FP32 flop/clk/CU
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
 FLOPS_PER_PAIR = 9          # 3 sub + 3 mul + 2 add (squared distance) + 1 compare
 NN_SOURCES = ["paper_2106_03287_amd/csrc/nn.hpp", "paper_2106_03287_amd/csrc/common.hpp"]
 
@@ -76,6 +77,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="kinect", choices=["cuboid", "kinect", "lidar", "batched"])
     ap.add_argument("--pairs", type=int, default=64, help="pairs of the batched workload")
+    ap.add_argument("--nn", default="fp32", choices=["fp32", "bf16"],
+                    help="nearest-neighbour search: exact FP32, or BF16 matrix-core screen + FP32 rerank")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -114,7 +117,8 @@ def main():
     theta0, sched = dev(prob.theta0), dev(prob.schedule)
     cfg = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m,
                                      schedule_rows=prob.schedule.shape[0], lr=prob.lr,
-                                     autotune=0 if args.tiling else args.autotune)
+                                     autotune=0 if args.tiling else args.autotune,
+                                     nn_mode=S.NN_BF16_RERANK if args.nn == "bf16" else S.NN_FP32)
     t_init = time.perf_counter()
     sol = S.SteinICP(cfg, src, ref, theta0, sched)
     init_ms = (time.perf_counter() - t_init) * 1e3
@@ -147,11 +151,34 @@ def main():
     nn_ms = sol.time_nn(max(20, min(200, int(200 / max(stage["nn"] / prob.T, 1e-3)))))
     pairs_per_launch = prob.K * prob.m * M
     achieved = pairs_per_launch * FLOPS_PER_PAIR / (nn_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(prob.name, tiling),
-                "kernel": "nn_fp32_kernel", "avg_launch_ms": round(nn_ms, 5),
-                "pair_evals_per_launch": pairs_per_launch}
+    if args.nn == "bf16":
+        # issued matrix-core work: one 16x16x32 BF16 MFMA (16384 flops) per
+        # 16 queries x 16 references, i.e. 64 flops per pair
+        mfma = pairs_per_launch * 64 / (nn_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "achieved": round(mfma, 3), "peak": MFMA_BF16_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(mfma / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
+                    "kernel": "nn_bf16_kernel", "avg_launch_ms": round(nn_ms, 5),
+                    "pair_evals_per_launch": pairs_per_launch,
+                    "alu_view": {"achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
+                                 "frac": round(achieved / VALU_PEAK_TFLOPS, 4)}}
+    else:
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
+                    "traffic": measured_traffic(prob.name, tiling),
+                    "kernel": "nn_fp32_kernel", "avg_launch_ms": round(nn_ms, 5),
+                    "pair_evals_per_launch": pairs_per_launch}
+    mismatch = None
+    if args.nn == "bf16":
+        # matches of the first iteration against the exact FP32 search from the same state
+        S.stein_icp_set_state(sol.ctx, theta0, zeros, zeros, 0)
+        sol.step(1)
+        mb = sol.diagnostics()["match"]
+        cfg32 = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m,
+                                           schedule_rows=prob.schedule.shape[0], lr=prob.lr)
+        ref32 = S.SteinICP(cfg32, src, ref, theta0, sched)
+        ref32.step(1)
+        mismatch = float((mb != ref32.diagnostics()["match"]).double().mean().item())
+        ref32.close()
     sol.close()
 
     out = {
@@ -165,16 +192,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16+f32" if args.nn == "bf16" else "f32",
         "data": "synthetic",
         "config": {"workload": prob.name, "K": prob.K, "m": prob.m, "T": prob.T,
-                   "N": len(prob.pair.src), "M": M, "nn": "fp32",
+                   "N": len(prob.pair.src), "M": M, "nn": args.nn,
                    "step": "one full solve of T iterations"},
         "nn_queries_per_s": round(queries_per_s, 1),
         "pair_evals_per_s": round(queries_per_s * M, 1),
         "stage_ms_per_iter": {k: round(v / prob.T, 5) for k, v in stage.items()},
         "init_ms": round(init_ms, 2),
         "nn_tiling": tiling,
+        "nn_mismatch_vs_fp32": mismatch,
         "nn_source_sha": nn_source_sha(),
         "torch": torch.__version__,
         "roofline": roofline,

@@ -9,7 +9,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 INCLUDE = os.path.join(ROOT, "include")
-SOURCES = [os.path.join(HERE, "stein_icp.hip")]
+# (source, extra flags): the BF16 screen is built with IEEE mode off
+SOURCES = [
+    (os.path.join(HERE, "stein_icp.hip"), []),
+    (os.path.join(HERE, "nn_bf16.hip"), ["-fno-honor-nans", "-mno-amdgpu-ieee"]),
+]
 OUT = os.path.join(PKG, "libstein_icp.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -26,9 +30,16 @@ FLAGS = [
 
 
 def build(out: str = OUT, extra=()) -> str:
+    objs = []
+    for src, flags in SOURCES:
+        obj = os.path.join(os.path.dirname(out), "_" + os.path.basename(src) + ".o")
+        cflags = [f for f in FLAGS if f != "-shared"]
+        subprocess.check_call([HIPCC, *cflags, *flags, *extra, f"-I{INCLUDE}", f"-I{HERE}", "-c", src, "-o", obj])
+        objs.append(obj)
     tmp = out + ".tmp"
-    cmd = [HIPCC, *FLAGS, *extra, f"-I{INCLUDE}", f"-I{HERE}", *SOURCES, "-o", tmp]
-    subprocess.check_call(cmd)
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
+    for o in objs:
+        os.remove(o)
     os.replace(tmp, out)
     return out
 

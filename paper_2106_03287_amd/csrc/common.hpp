@@ -26,6 +26,8 @@ struct PairDesc {
     int64_t n_scale;    // N in "N gbar"
     int64_t q_off;      // into the float4 query buffer
     int64_t nq;         // queries of this pair (K * m in a solver context)
+    int64_t apack_off;  // into the BF16 reference fragments (64 per 16 references)
+    float c0[4];        // reference centroid (centres the BF16 screen)
     int32_t chunks;     // reference chunks, one partial argmin each
     int32_t chunk;      // references per chunk (multiple of 4 * kTile)
     int32_t qblocks;    // query blocks of kWave * Q queries

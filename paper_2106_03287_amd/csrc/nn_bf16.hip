@@ -1,0 +1,37 @@
+// Translation unit of the BF16-screen nearest-neighbour kernels (built with
+// -fno-honor-nans -mno-amdgpu-ieee; see nn_bf16_launch.h).
+#include "nn_bf16.hpp"
+
+namespace sicp {
+
+template <int Q>
+static void launch_q(int w, unsigned grid, const NNBf16Args& a, hipStream_t s)
+{
+    switch (w) {
+    case 4: hipLaunchKernelGGL((nn_bf16_kernel<Q, 4>), dim3(grid), dim3(kWave * 4), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((nn_bf16_kernel<Q, 8>), dim3(grid), dim3(kWave * 8), 0, s, a); break;
+    default: hipLaunchKernelGGL((nn_bf16_kernel<Q, 16>), dim3(grid), dim3(kWave * 16), 0, s, a); break;
+    }
+}
+
+hipError_t launch_nn_bf16_kernel(int q, int w, unsigned grid, const NNBf16Args& a, hipStream_t s)
+{
+    if (w != 4 && w != 8 && w != 16) return hipErrorInvalidValue;
+    switch (q) {
+    case 1: launch_q<1>(w, grid, a, s); break;
+    case 2: launch_q<2>(w, grid, a, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_bf16(const PairDesc* pairs, int32_t n_pairs, int64_t max_blocks, const float4* ref4,
+                            uint4* apack, hipStream_t s)
+{
+    if (n_pairs < 1 || max_blocks < 1) return hipSuccess;
+    hipLaunchKernelGGL(pack_bf16_refs_kernel, dim3((unsigned)((max_blocks + 3) / 4), (unsigned)n_pairs), dim3(256), 0,
+                       s, pairs, ref4, apack);
+    return hipGetLastError();
+}
+
+}  // namespace sicp

@@ -1,0 +1,228 @@
+// Nearest neighbour (Eq. 1) with a BF16 matrix-core screen and an exact FP32
+// rerank.
+//
+// Screen: squared distances in the expanded form |q|^2 + |r|^2 - 2 q.r on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation. Both sides are centred on
+// the pair's reference centroid c0, and every FP32 value is split into three
+// BF16 parts (x = h + m + l, the usual BF16x3 decomposition), so each product
+// keeps about 24 bits; 24 of the 32 K slots are used:
+//    k  0- 2: r_h  * -2 q_h      k  9-11: r_h * -2 q_l      k 18-20: |r|^2 (h, m, l) * 1
+//    k  3- 5: r_h  * -2 q_m      k 12-14: r_l * -2 q_h      k 21-23: 1 * |q|^2 (h, m, l)
+//    k  6- 8: r_m  * -2 q_h      k 15-17: r_m * -2 q_m      k 24-31: 0
+// The references are the A operand (16 per block, pre-packed in the lane
+// layout at init), the queries the B operand (16 per group, built once per
+// wavefront). Lane l owns query l % 16 of each group and receives rows
+// 4 (l / 16) .. +3 of each 16-reference block; it keeps only the minimum of
+// those four values and the block where it fell.
+//
+// Rerank: each lane recomputes the exact FP32 distance (the same operation
+// sequence as the FP32 search) of its four references in its best block; the
+// four lanes of a query merge their (distance, tile) keys. The key format is
+// the FP32 search's, so chunk reduction and tile resolution downstream are
+// shared. The screen can miss the true neighbour when BF16 rounding reorders
+// near-equal candidates; the result is then another reference with its exact
+// distance (the miss rate is measured by the tests).
+#pragma once
+
+#include "common.hpp"
+#include "nn_bf16_launch.h"
+
+namespace sicp {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
+
+// Round to nearest even BF16 (finite inputs), returned as bits.
+__device__ __forceinline__ uint16_t bf16_bits(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// x = h + m + l with each part BF16 (each subtraction is exact in FP32).
+__device__ __forceinline__ void split3(float x, uint16_t& h, uint16_t& m, uint16_t& l)
+{
+#pragma clang fp contract(off)
+    h = bf16_bits(x);
+    const float r1 = x - bf16_float(h);
+    m = bf16_bits(r1);
+    const float r2 = r1 - bf16_float(m);
+    l = bf16_bits(r2);
+}
+
+constexpr uint16_t kBf16One = 0x3F80;
+constexpr uint16_t kBf16Zero = 0;
+
+// The eight K slots 8 s .. 8 s + 7 of one side. `ref` selects the A (reference)
+// or B (query) column of the slot table above.
+__device__ __forceinline__ u16x8_t slot_fragment(const float c[3], bool ref, int s)
+{
+#pragma clang fp contract(off)
+    uint16_t h[3], m[3], l[3], nh, nm, nl;
+    for (int d = 0; d < 3; ++d) split3(c[d], h[d], m[d], l[d]);
+    const float n = (c[0] * c[0] + c[1] * c[1]) + c[2] * c[2];
+    split3(n, nh, nm, nl);
+    uint16_t t[32];
+    if (ref) {
+        for (int d = 0; d < 3; ++d) {
+            t[d] = h[d]; t[3 + d] = h[d]; t[6 + d] = m[d];
+            t[9 + d] = h[d]; t[12 + d] = l[d]; t[15 + d] = m[d];
+            t[21 + d] = kBf16One;
+        }
+        t[18] = nh; t[19] = nm; t[20] = nl;
+    } else {
+        // -2 x of a BF16 value is exact in FP32 and again a BF16 value
+        auto m2 = [](uint16_t v) -> uint16_t { return bf16_bits(-2.0f * bf16_float(v)); };
+        for (int d = 0; d < 3; ++d) {
+            t[d] = m2(h[d]); t[3 + d] = m2(m[d]); t[6 + d] = m2(h[d]);
+            t[9 + d] = m2(l[d]); t[12 + d] = m2(h[d]); t[15 + d] = m2(m[d]);
+            t[18 + d] = kBf16One;
+        }
+        t[21] = nh; t[22] = nm; t[23] = nl;
+    }
+    for (int k = 24; k < 32; ++k) t[k] = kBf16Zero;
+    u16x8_t v;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        uint16_t x = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (s == q) x = t[8 * q + k];
+        v[k] = x;
+    }
+    return v;
+}
+
+// grid (blocks of 16 references, pairs) x 64 lanes: A fragments of the
+// centred references, 16 bytes per lane and block.
+__global__ void pack_bf16_refs_kernel(const PairDesc* __restrict__ pairs, const float4* __restrict__ ref4,
+                                      uint4* __restrict__ apack)
+{
+    const PairDesc pd = pairs[blockIdx.y];
+    const int64_t blk = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    if (blk >= pd.n_ref_pad / kTile) return;
+    const float4 r = ref4[pd.ref_off + blk * kTile + (lane & 15)];
+    float c[3];
+    {
+#pragma clang fp contract(off)
+        c[0] = r.x - pd.c0[0];
+        c[1] = r.y - pd.c0[1];
+        c[2] = r.z - pd.c0[2];
+    }
+    const u16x8_t v = slot_fragment(c, true, lane >> 4);
+    apack[pd.apack_off + blk * kWave + lane] = __builtin_bit_cast(uint4, v);
+}
+
+
+// A work item holds 64 Q queries (as in the FP32 search), taken as 4 Q groups
+// of 16 by every wavefront of the workgroup.
+template <int Q, int W>
+__device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem w, uint64_t (*sk)[kWave * Q])
+{
+    constexpr int G = 4 * Q;   // query groups of 16
+    const PairDesc pd = a.pairs[w.pair];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = uniform(threadIdx.x >> 6);
+    const int64_t nq = pd.nq;
+    const int64_t qbase = (int64_t)w.qblock * kWave * Q;
+    const int j = lane & 15, s = lane >> 4;
+
+    bf16x8_t bfrag[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t qi = qbase + 16 * g + j;
+        const float4 qf = qi < nq ? a.queries[pd.q_off + qi] : make_float4(0.f, 0.f, 0.f, 0.f);
+        float c[3];
+        {
+#pragma clang fp contract(off)
+            c[0] = qf.x - pd.c0[0];
+            c[1] = qf.y - pd.c0[1];
+            c[2] = qf.z - pd.c0[2];
+        }
+        bfrag[g] = __builtin_bit_cast(bf16x8_t, slot_fragment(c, false, s));
+    }
+
+    const int64_t c0 = (int64_t)w.chunk * pd.chunk;
+    const int64_t cend = min(c0 + (int64_t)pd.chunk, pd.n_ref_pad);
+    const int64_t ntiles = (cend - c0) / kTile;
+    const int64_t t0 = (ntiles * wave) / W;
+    const int64_t t1 = (ntiles * (wave + 1)) / W;
+    const uint4* __restrict__ ap = a.apack + pd.apack_off + (c0 / kTile) * kWave + lane;
+
+    float best[G];
+    int32_t bblk[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        best[g] = __builtin_inff();
+        bblk[g] = (int32_t)t0;
+    }
+    uint4 anext = t0 < t1 ? ap[t0 * kWave] : make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t tt = t0; tt < t1; ++tt) {
+        const bf16x8_t afrag = __builtin_bit_cast(bf16x8_t, anext);
+        if (tt + 1 < t1) anext = ap[(tt + 1) * kWave];   // next block's fragment in flight
+        // all groups' products first (independent accumulators keep the
+        // matrix pipeline busy), then the minimum epilogues
+        f32x4_t acc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const f32x4_t zero = {0.f, 0.f, 0.f, 0.f};
+            acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[g], zero, 0, 0, 0);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const float mn = __builtin_fminf(__builtin_fminf(acc[g][0], acc[g][1]), __builtin_fminf(acc[g][2], acc[g][3]));
+            const bool better = mn < best[g];
+            best[g] = better ? mn : best[g];
+            bblk[g] = better ? (int32_t)tt : bblk[g];
+        }
+    }
+
+    // exact FP32 rerank of the lane's four references in its best block,
+    // then the minimum over the four lanes of each query
+    const float4* __restrict__ rp = a.ref4 + pd.ref_off + c0;
+    uint64_t key[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t qi = qbase + 16 * g + j;
+        const float4 qf = qi < nq ? a.queries[pd.q_off + qi] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4* __restrict__ r = rp + (int64_t)bblk[g] * kTile + 4 * s;
+        float bd = __builtin_inff();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float4 rr = r[u];
+            bd = __builtin_fminf(bd, dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z));
+        }
+        uint64_t k = (t0 < t1) ? pack_key(bd, (uint32_t)(c0 / kTile + bblk[g])) : ~0ull;
+        k = min(k, (uint64_t)__shfl_xor((unsigned long long)k, 16));
+        k = min(k, (uint64_t)__shfl_xor((unsigned long long)k, 32));
+        key[g] = k;
+    }
+
+    // lanes 0..15 hold the merged keys of the G groups; merge the W waves
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+        if (s == 0) sk[wave][16 * g + j] = key[g];
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < kWave * Q; jj += kWave * W) {
+        const int64_t qi = qbase + jj;
+        if (qi < nq) {
+            uint64_t k0 = sk[0][jj];
+#pragma unroll
+            for (int v = 1; v < W; ++v) k0 = min(k0, sk[v][jj]);
+            a.partial[pd.part_off + (int64_t)w.chunk * nq + qi] = k0;
+        }
+    }
+    __syncthreads();
+}
+
+template <int Q, int W>
+__global__ __launch_bounds__(kWave * W) void nn_bf16_kernel(NNBf16Args a)
+{
+    __shared__ uint64_t sk[W][kWave * Q];
+    for (int64_t it = blockIdx.x; it < a.nwork; it += gridDim.x) nn_bf16_item<Q, W>(a, a.work[it], sk);
+}
+
+}  // namespace sicp

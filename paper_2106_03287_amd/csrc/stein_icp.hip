@@ -16,6 +16,7 @@
 #include "common.hpp"
 #include "grad.hpp"
 #include "nn.hpp"
+#include "nn_bf16_launch.h"
 #include "prep.hpp"
 #include "svgd.hpp"
 
@@ -145,6 +146,7 @@ struct stein_icp_ctx {
     int64_t* step = nullptr;
     Pose* pose = nullptr;
     float4* queries = nullptr;   // FP32 queries of the coming iteration, K*m per pair
+    uint4* apack = nullptr;      // BF16 reference fragments (BF16 screen only)
     int32_t* match = nullptr;
     double* dscr = nullptr;
     int* flag = nullptr;
@@ -202,8 +204,6 @@ int validate_config(const stein_icp_config* c)
         if (!std::isfinite(c->init_centre[i])) return fail(STEIN_ICP_E_INVALID, "init_centre must be finite");
     if (c->nn_mode != STEIN_ICP_NN_FP32 && c->nn_mode != STEIN_ICP_NN_BF16_RERANK)
         return fail(STEIN_ICP_E_INVALID, "unknown nn_mode");
-    if (c->nn_mode == STEIN_ICP_NN_BF16_RERANK)
-        return fail(STEIN_ICP_E_INVALID, "nn_mode BF16_RERANK is not available in this build");
     if (c->optimizer != STEIN_ICP_OPT_ADAM && c->optimizer != STEIN_ICP_OPT_SGD)
         return fail(STEIN_ICP_E_INVALID, "unknown optimizer");
     if (c->bandwidth_mode != STEIN_ICP_BW_MEDIAN && c->bandwidth_mode != STEIN_ICP_BW_FIXED)
@@ -232,6 +232,8 @@ constexpr int64_t kMaxRef = ((int64_t)1 << 31) - 64;
 
 dim3 grid1d(int64_t n, int threads) { return dim3((unsigned)ceil_div(std::max<int64_t>(n, 1), threads)); }
 
+int g_num_cus = 256;
+
 // Launch the NN kernel with q queries per lane and w wavefronts per workgroup.
 template <int Q>
 void launch_nn_q(int w, unsigned nwork, const NNArgs& a, hipStream_t s)
@@ -243,7 +245,15 @@ void launch_nn_q(int w, unsigned nwork, const NNArgs& a, hipStream_t s)
     }
 }
 
-int g_num_cus = 256;
+// BF16 screen + FP32 rerank with the same work table and key format.
+hipError_t launch_nn_bf16(const Tiling& t, unsigned nwork, NNBf16Args a, hipStream_t s)
+{
+    if (nwork == 0) return hipSuccess;
+    if (t.w != 4 && t.w != 8 && t.w != 16) return hipErrorInvalidValue;
+    a.nwork = nwork;
+    const unsigned grid = t.persist > 0 ? std::min<unsigned>(nwork, (unsigned)(t.persist * g_num_cus)) : nwork;
+    return launch_nn_bf16_kernel(t.q, t.w, grid, a, s);
+}
 
 hipError_t launch_nn(const Tiling& t, unsigned nwork, NNArgs a, hipStream_t s)
 {
@@ -357,7 +367,19 @@ hipError_t enqueue_queries(const stein_icp_ctx* c, hipStream_t s)
 // direction, update and commit.
 hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
 {
-    if (stage == 0) return launch_nn(c->tiling, (unsigned)c->work.size(), nn_args(c), s);
+    if (stage == 0) {
+        if (c->cfg.nn_mode == STEIN_ICP_NN_BF16_RERANK) {
+            NNBf16Args b{};
+            b.work = c->d_work;
+            b.pairs = c->d_pairs;
+            b.ref4 = c->ref4;
+            b.apack = c->apack;
+            b.queries = c->queries;
+            b.partial = c->partial;
+            return launch_nn_bf16(c->tiling, (unsigned)c->work.size(), b, s);
+        }
+        return launch_nn(c->tiling, (unsigned)c->work.size(), nn_args(c), s);
+    }
     if (stage == 1) {
     GradArgs g{};
     g.pairs = c->d_pairs;
@@ -493,9 +515,11 @@ int autotune(stein_icp_ctx* c, hipStream_t s)
     double best = 1e30;
     Tiling best_t = c->tiling;
     std::set<std::vector<int32_t>> seen;
+    const bool bf16 = c->cfg.nn_mode == STEIN_ICP_NN_BF16_RERANK;
     for (int q : {1, 2, 4})
         for (int w : {4, 8, 16})
             for (int64_t pw : {64, 128, 256, 512, 1024, 2048, 4096}) {
+                if (bf16 && q > 2) continue;
                 Tiling t;
                 t.q = q;
                 t.w = w;
@@ -626,8 +650,28 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
         c->pairs.push_back(pd);
     }
     c->tiling = default_tiling(c->pairs, nq);
+    if (cfg->nn_mode == STEIN_ICP_NN_BF16_RERANK && c->tiling.q > 2) c->tiling.q = 2;
     HIP_TRY(hipFuncSetAttribute((const void*)svgd_bandwidth_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)bandwidth_lds_bytes(K)));
+    const bool bf16 = cfg->nn_mode == STEIN_ICP_NN_BF16_RERANK;
+    int64_t apack_n = 0;
+    if (bf16) {
+        std::vector<float> h;
+        for (int32_t p = 0; p < P; ++p) {
+            PairDesc& pd = c->pairs[p];
+            h.resize((size_t)pd.n_ref * 3);
+            if (hipMemcpy(h.data(), ref[p], 12 * (size_t)pd.n_ref, hipMemcpyDeviceToHost) != hipSuccess) {
+                delete c;
+                return fail(STEIN_ICP_E_DEVICE, "reading the reference cloud for its centroid failed");
+            }
+            double acc[3] = {0, 0, 0};
+            for (int64_t i = 0; i < pd.n_ref; ++i)
+                for (int d = 0; d < 3; ++d) acc[d] += h[3 * i + d];
+            for (int d = 0; d < 3; ++d) pd.c0[d] = std::isfinite(acc[d]) ? (float)(acc[d] / pd.n_ref) : 0.0f;
+            pd.apack_off = apack_n;
+            apack_n += pd.n_ref_pad / kTile * kWave;
+        }
+    }
     const int64_t PK6 = (int64_t)P * K * 6;
     const int64_t npairs2 = K >= 2 ? (int64_t)K * (K - 1) : 1;
     size_t off = 0;
@@ -646,6 +690,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     const size_t o_step = take(8 * (size_t)P);
     const size_t o_pose = take(sizeof(Pose) * (size_t)P * K);
     const size_t o_queries = take(sizeof(float4) * (size_t)P * nq);
+    const size_t o_apack = take(sizeof(uint4) * (size_t)std::max<int64_t>(apack_n, 1));
     const size_t o_match = take(4 * (size_t)P * nq);
     const size_t o_dscr = take(8 * (size_t)P * npairs2);
     const size_t o_flag = take(64);
@@ -668,6 +713,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     c->step = (int64_t*)(c->arena + o_step);
     c->pose = (Pose*)(c->arena + o_pose);
     c->queries = (float4*)(c->arena + o_queries);
+    c->apack = (uint4*)(c->arena + o_apack);
     c->match = (int32_t*)(c->arena + o_match);
     c->dscr = (double*)(c->arena + o_dscr);
     c->flag = (int*)(c->arena + o_flag);
@@ -713,6 +759,12 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     if (hipMemcpyAsync(c->d_pairs, c->pairs.data(), sizeof(PairDesc) * P, hipMemcpyHostToDevice, s) != hipSuccess)
         return bail(fail(STEIN_ICP_E_DEVICE, "pair table upload failed"));
     if (enqueue_queries(c, s) != hipSuccess) return bail(fail(STEIN_ICP_E_DEVICE, "query kernel launch failed"));
+    if (bf16) {
+        int64_t maxblk = 0;
+        for (const auto& pd : c->pairs) maxblk = std::max<int64_t>(maxblk, pd.n_ref_pad / kTile);
+        if (launch_pack_bf16(c->d_pairs, P, maxblk, c->ref4, c->apack, s) != hipSuccess)
+            return bail(fail(STEIN_ICP_E_DEVICE, "BF16 packing launch failed"));
+    }
     int flag = 0;
     if (hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -960,7 +1012,7 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
 {
     if (nq < 0 || n_ref < 1) return fail(STEIN_ICP_E_INVALID, "need nq >= 0 and n_ref >= 1");
     if (nq > kMaxRef || n_ref > kMaxRef) return fail(STEIN_ICP_E_INVALID, "sizes must be below 2^31 - 64");
-    if (mode != STEIN_ICP_NN_FP32) return fail(STEIN_ICP_E_INVALID, "unknown or unavailable nn mode");
+    if (mode != STEIN_ICP_NN_FP32 && mode != STEIN_ICP_NN_BF16_RERANK) return fail(STEIN_ICP_E_INVALID, "unknown nn mode");
     if (nq == 0) return STEIN_ICP_OK;
     if (!q_xyz || !ref_xyz || !idx) return fail(STEIN_ICP_E_INVALID, "a pointer is NULL");
     hipStream_t s = (hipStream_t)hip_stream;
@@ -969,8 +1021,20 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     pd.nq = nq;
     pd.n_ref = n_ref;
     pd.n_ref_pad = round_up(n_ref, kTile);
+    const bool bf16 = mode == STEIN_ICP_NN_BF16_RERANK;
+    if (bf16) {
+        std::vector<float> h((size_t)n_ref * 3);
+        if (hipMemcpy(h.data(), ref_xyz, 12 * (size_t)n_ref, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(STEIN_ICP_E_DEVICE, "reading the reference cloud for its centroid failed");
+        double acc[3] = {0, 0, 0};
+        for (int64_t i = 0; i < n_ref; ++i)
+            for (int d = 0; d < 3; ++d) acc[d] += h[3 * i + d];
+        for (int d = 0; d < 3; ++d) pd.c0[d] = std::isfinite(acc[d]) ? (float)(acc[d] / n_ref) : 0.0f;
+        pd.apack_off = 0;
+    }
     std::vector<PairDesc> v{pd};
     Tiling t = default_tiling(v, nq);
+    if (bf16 && t.q > 2) t.q = 2;
     pd.chunk = t.chunk[0];
     pd.chunks = (int32_t)ceil_div(pd.n_ref_pad, pd.chunk);
     pd.qblocks = (int32_t)ceil_div(nq, (int64_t)kWave * t.q);
@@ -986,6 +1050,7 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     const size_t o_q = take(16 * (size_t)nq), o_r = take(16 * (size_t)pd.n_ref_pad);
     const size_t o_p = take(8 * (size_t)pd.chunks * nq), o_w = take(sizeof(WorkItem) * work.size());
     const size_t o_d = take(sizeof(PairDesc)), o_f = take(64);
+    const size_t o_ap = take(bf16 ? sizeof(uint4) * (size_t)(pd.n_ref_pad / kTile * kWave) : 16);
     char* mem = nullptr;
     if (hipMalloc(&mem, off) != hipSuccess) {
         (void)hipGetLastError();
@@ -1014,7 +1079,19 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess && flag) rc = fail(STEIN_ICP_E_INVALID, "a coordinate is non-finite or above 1e9");
     if (e == hipSuccess && !rc) {
-        e = launch_nn(t, (unsigned)work.size(), a, s);
+        if (bf16) {
+            e = launch_pack_bf16(a.pairs, 1, pd.n_ref_pad / kTile, a.ref4, (uint4*)(mem + o_ap), s);
+            NNBf16Args b{};
+            b.work = a.work;
+            b.pairs = a.pairs;
+            b.ref4 = a.ref4;
+            b.apack = (const uint4*)(mem + o_ap);
+            b.queries = a.queries;
+            b.partial = a.partial;
+            if (e == hipSuccess) e = launch_nn_bf16(t, (unsigned)work.size(), b, s);
+        } else {
+            e = launch_nn(t, (unsigned)work.size(), a, s);
+        }
         if (e == hipSuccess) {
             hipLaunchKernelGGL(nn_finish_kernel, grid1d(nq, 256), dim3(256), 0, s, a.partial, a.queries, a.ref4,
                                pd.n_ref_pad, nq, pd.chunks, idx, d2);

@@ -376,3 +376,70 @@ def test_batched_uneven_pairs_tuned_and_persistent():
         np.testing.assert_array_equal(outs[0][i], gpu_run(p, 5))
         if i < 2:
             assert_poses_close(outs[0][i], oracle_run(p, 5))
+
+
+# ------------------------------------------------------------------ BF16 screen + FP32 rerank
+
+def _bf16_check(q, ref, min_recall):
+    idx, d2 = S.stein_icp_nn(dev(q), dev(ref), mode=S.NN_BF16_RERANK)
+    idx, d2 = idx.cpu().numpy(), d2.cpu().numpy()
+    oi, od = oracle.nn_f32(q, ref)
+    # every answer is a real reference with its exact FP32 distance, never
+    # below the true minimum; most answers are the exact neighbour
+    exact = np.array([oracle.dist2_f32(q[i], ref[idx[i]]) for i in range(len(q))], np.float32)
+    np.testing.assert_array_equal(d2, exact)
+    assert np.all(d2 >= od)
+    recall = float(np.mean(idx == oi))
+    print(f"bf16 recall {recall:.5f} over {len(q)} queries, max d2 excess "
+          f"{float(np.max(d2 - od)):.3e}", flush=True)
+    assert recall >= min_recall
+    return recall
+
+
+def test_bf16_screen_kinect_queries():
+    prob = synth.make_problem("kinect", 0, T=1)
+    rng = np.random.default_rng(8)
+    sel = rng.choice(len(prob.pair.src), 4000, replace=False)
+    q = np.concatenate([oracle.transform(prob.theta0[k], prob.pair.src[sel[k::8]]) for k in range(8)])
+    _bf16_check(q.astype(np.float32), prob.pair.ref, 0.995)
+
+
+def test_bf16_screen_lidar_queries():
+    prob = synth.make_problem("lidar", 0, K=1, T=1)
+    rng = np.random.default_rng(9)
+    sel = rng.choice(len(prob.pair.src), 3000, replace=False)
+    q = oracle.transform(prob.theta0[0], prob.pair.src[sel]).astype(np.float32)
+    _bf16_check(q, prob.pair.ref, 0.98)
+
+
+@pytest.mark.parametrize("nq,M", [(1, 1), (100, 17), (4097, 2000), (0, 5)])
+def test_bf16_screen_ragged_sizes(nq, M):
+    rng = np.random.default_rng(nq + 7 * M)
+    ref = rng.uniform(-1, 1, (M, 3)).astype(np.float32)
+    q = rng.uniform(-1.2, 1.2, (nq, 3)).astype(np.float32)
+    if nq == 0:
+        S.stein_icp_nn(dev(q).reshape(-1, 3), dev(ref), mode=S.NN_BF16_RERANK)
+        return
+    _bf16_check(q, ref, 0.99)
+
+
+def test_bf16_solver_against_oracle():
+    prob = synth.make_problem("kinect", 0, T=10)
+    opts = {}
+    gcfg, ocfg = both_configs(prob, opts)
+    gcfg.nn_mode = S.NN_BF16_RERANK
+    sol = S.SteinICP(gcfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule))
+    sol.step(1)
+    match = sol.diagnostics()["match"].cpu().numpy()[0]
+    sol.step(prob.T - 1)
+    got = sol.particles().cpu().numpy()[0]
+    sol.close()
+    st = oracle.State(prob.theta0)
+    od = oracle.step(ocfg, prob.pair.src, prob.pair.ref, prob.schedule[0], st)
+    mismatch = float(np.mean(match != od["match"]))
+    oracle.run(ocfg, prob.pair.src, prob.pair.ref, prob.schedule, prob.T - 1, st)
+    d = np.abs(wrapped(got - st.theta))
+    print(f"bf16 solver: first-iteration match mismatch {mismatch:.2e}; after {prob.T} iterations "
+          f"max |dtheta| {d.max():.3e}", flush=True)
+    assert mismatch <= 5e-3
+    assert d.max() <= 1e-2
