@@ -1,0 +1,218 @@
+"""Pins of the proposal-network oracle (CPU): every check compares it with
+something other than itself -- torch's BF16 conversion, a hand-built network
+with a closed-form output, central finite differences, closed forms of the
+MMD^2 and of Adam's first steps."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import proposal_oracle as PO
+
+
+def _rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+# ------------------------------------------------------------------ rounding
+def test_bf16_rounding_matches_torch_conversion():
+    r = _rng(1)
+    x = np.concatenate([
+        r.standard_normal(20000) * 10.0 ** r.integers(-6, 6, 20000),
+        # exact ties between two BF16 values: round to even
+        (1.0 + np.arange(0, 64) * 2.0 ** -7 + 2.0 ** -8),
+        [0.0, -0.0, 1e-40, -1e-40, 3.4e38, np.inf, -np.inf],
+    ]).astype(np.float32)
+    want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    got = PO.bf16_round(x)
+    assert np.array_equal(got, want)
+    assert np.isnan(PO.bf16_round(np.array([np.nan]))).all()
+
+
+def test_bf16_rounding_goes_through_fp32_first():
+    # 1 + 2^-8 + 2^-30 lies above the BF16 tie in FP64 but rounds to the
+    # tie 1 + 2^-8 in FP32 first, which then rounds to even (1.0)
+    x = 1.0 + 2.0 ** -8 + 2.0 ** -30
+    assert PO.bf16_round(np.array([x]))[0] == 1.0
+
+
+# --------------------------------------------------------------- structure
+def _closed_form_network(K=2):
+    b = {k: np.zeros(s) for k, (o, s) in PO.layout(K).items()}
+    for d in range(3):
+        b["W1"][d, d] = 1.0          # relu(x)
+        b["W1"][d, 3 + d] = -1.0     # relu(-x)
+    b["b1"][6] = 0.5                 # constant feature
+    for j in range(7):
+        b["W2"][j, j] = 1.0
+        b["W3"][j, j] = 1.0
+        b["W4"][j, j] = 1.0          # source features -> z[0:7]
+        b["W4"][256 + j, 7 + j] = 1.0  # reference features -> z[7:14]
+    b["b4"][20] = 0.25
+    for d in range(3):
+        b["W5"][7 + d, d] = 1.0      # particle 0: max_ref - max_src
+        b["W5"][d, d] = -1.0
+        b["W5"][10 + d, 6 + d] = -1.0  # particle 1: -(relu(-min_ref) - relu(-min_src))
+        b["W5"][3 + d, 6 + d] = 1.0
+    b["W5"][20, 3] = 2.0
+    b["b5"][4] = 0.1
+    b["b5"][11] = -0.3
+    return PO.pack(b, K)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_forward_of_hand_built_network_has_closed_form(bf16):
+    r = _rng(2)
+    K = 2
+    params = _closed_form_network(K)
+    # coordinates on a 1/8 grid (exact in BF16); the reference cloud lies
+    # entirely below z = 0, so its pooled relu(z) is clipped to 0
+    src = r.integers(-16, 17, (37, 3)) / 8.0
+    ref = r.integers(-16, 17, (37, 3)) / 8.0
+    ref[:, 2] = -np.abs(ref[:, 2]) - 0.125
+    out = PO.forward(params, np.stack([src, ref])[None], K, bf16=bf16)["Y"][0]
+    relu = lambda a: np.maximum(a, 0.0)
+    want = np.zeros((K, 6))
+    want[0, :3] = relu(ref.max(0)) - relu(src.max(0))
+    want[1, :3] = -(relu(-ref.min(0)) - relu(-src.min(0)))
+    want[0, 3] = 0.5
+    want[0, 4] = 0.1
+    want[1, 5] = -0.3
+    assert np.array_equal(out, want)
+    assert want[0, 2] == -relu(src.max(0))[2]     # the clipped feature matters
+
+
+def test_output_is_invariant_under_point_order_and_depends_on_pair_order():
+    r = _rng(3)
+    K = 3
+    params = r.standard_normal(PO.param_count(K)) * 0.2
+    clouds = r.standard_normal((1, 2, 50, 3))
+    y = PO.forward(params, clouds, K)["Y"]
+    shuffled = clouds.copy()
+    shuffled[0, 0] = clouds[0, 0][r.permutation(50)]
+    shuffled[0, 1] = clouds[0, 1][r.permutation(50)]
+    assert np.array_equal(PO.forward(params, shuffled, K)["Y"], y)
+    swapped = clouds[:, ::-1].copy()
+    assert not np.allclose(PO.forward(params, swapped, K)["Y"], y)
+
+
+def test_subsample_takes_every_point_once_or_repeats_evenly():
+    pts = np.arange(30, dtype=np.float32).reshape(10, 3)
+    assert np.array_equal(PO.subsample(pts, 10), pts)
+    rep = PO.subsample(pts, 40)
+    assert np.array_equal(rep[::4], pts) and np.array_equal(rep[3::4], pts)
+    sub = PO.subsample(np.arange(300).reshape(100, 3), 7)
+    assert list(sub[:, 0] // 3) == [0, 14, 28, 42, 57, 71, 85]
+
+
+# -------------------------------------------------------------------- MMD^2
+SIG = np.array([[0.5, 0.5, 0.5, 0.3, 0.3, 0.3], [2.0, 2.0, 2.0, 1.0, 1.0, 1.0]])
+
+
+def test_mmd_closed_form_for_single_particles():
+    x = np.array([[0.1, -0.2, 0.3, 0.4, -0.5, 0.6]])
+    y = np.array([[0.0, 0.1, 0.2, -0.3, 0.2, 0.1]])
+    d = x - y
+    k = sum(np.exp(-0.5 * np.sum((d / s) ** 2)) for s in SIG)
+    assert PO.mmd2(x, y, SIG) == pytest.approx(2 * len(SIG) - 2 * k, rel=1e-14)
+
+
+def test_mmd_is_zero_on_equal_sets_positive_otherwise_and_permutation_free():
+    r = _rng(4)
+    X = r.standard_normal((20, 6))
+    Y = r.standard_normal((20, 6))
+    assert abs(PO.mmd2(X, X, SIG)) < 1e-14
+    assert abs(PO.mmd2(X, X[r.permutation(20)], SIG)) < 1e-14
+    v = PO.mmd2(X, Y, SIG)
+    assert v > 0
+    assert PO.mmd2(X[r.permutation(20)], Y[r.permutation(20)], SIG) == pytest.approx(v, rel=1e-12)
+    assert PO.mmd2(Y, X, SIG) == pytest.approx(v, rel=1e-12)
+
+
+def test_mmd_wraps_angles():
+    r = _rng(5)
+    X = r.standard_normal((8, 6))
+    Y = X.copy()
+    Y[:, 3:] += 2 * np.pi * r.integers(-2, 3, (8, 3))
+    assert abs(PO.mmd2(X, Y, SIG)) < 1e-12
+    Z = X.copy()
+    Z[:, :3] += 2 * np.pi          # translations do not wrap
+    assert PO.mmd2(X, Z, SIG) > 0.1
+
+
+def test_mmd_gradient_matches_finite_differences():
+    r = _rng(6)
+    X = r.standard_normal((6, 6))
+    Y = r.standard_normal((6, 6))
+    g = PO.mmd2_grad(X, Y, SIG)
+    h = 1e-6
+    for i in range(6):
+        for c in range(6):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[i, c] += h
+            Xm[i, c] -= h
+            fd = (PO.mmd2(Xp, Y, SIG) - PO.mmd2(Xm, Y, SIG)) / (2 * h)
+            assert g[i, c] == pytest.approx(fd, abs=1e-8)
+
+
+# ----------------------------------------------------------------- backward
+def _small_problem(seed=7, K=2, P=6, B=2):
+    r = _rng(seed)
+    L = PO.layout(K)
+    blocks = {}
+    for name, (o, s) in L.items():
+        fan_in = s[0] if len(s) == 2 else 1
+        blocks[name] = r.standard_normal(s) / np.sqrt(fan_in) + (0.1 if len(s) == 1 else 0.0)
+    params = PO.pack(blocks, K)
+    clouds = r.standard_normal((B, 2, P, 3))
+    targets = r.standard_normal((B, K, 6))
+    return params, clouds, targets, K
+
+
+def test_network_gradient_matches_finite_differences():
+    params, clouds, targets, K = _small_problem()
+    sig = np.array([[1.0] * 6, [3.0] * 6])
+    _, g, cache = PO.loss_and_grad(params, clouds, targets, K, sig, bf16=False)
+    assert PO.pool_margin(cache) > 1e-4     # far from a tie at the step h below
+    L = PO.layout(K)
+    r = _rng(8)
+    idx = []
+    for name, (o, s) in L.items():
+        n = int(np.prod(s))
+        idx += list(o + (np.arange(n) if n <= 64 else r.choice(n, 48, replace=False)))
+    h = 1e-6
+    for i in idx:
+        p1, p2 = params.copy(), params.copy()
+        p1[i] += h
+        p2[i] -= h
+        fd = (PO.loss_only(p1, clouds, targets, K, sig) - PO.loss_only(p2, clouds, targets, K, sig)) / (2 * h)
+        assert g[i] == pytest.approx(fd, abs=2e-8, rel=1e-5), i
+    # every block receives gradient (nothing is silently cut off)
+    for name, (o, s) in L.items():
+        assert np.any(g[o:o + int(np.prod(s))] != 0), name
+
+
+def test_bf16_gradient_stays_close_to_the_fp64_one():
+    # one point per cloud: no max-pool decision that rounding could flip
+    # (BF16 operands change individual terms by up to 2^-8 relative; sums
+    # with cancellation and ReLU decisions near 0 amplify that, so only the
+    # direction is pinned)
+    for seed in range(9, 16):
+        params, clouds, targets, K = _small_problem(seed=seed, P=1)
+        sig = np.array([[1.0] * 6])
+        _, g64, _ = PO.loss_and_grad(params, clouds, targets, K, sig, bf16=False)
+        _, g16, _ = PO.loss_and_grad(params, clouds, targets, K, sig, bf16=True)
+        cos = g16 @ g64 / (np.linalg.norm(g16) * np.linalg.norm(g64))
+        assert cos > 0.98
+        assert not np.array_equal(g16, g64)
+
+
+# --------------------------------------------------------------------- Adam
+def test_adam_first_steps_move_by_lr_against_the_gradient_sign():
+    w = np.array([1.0, -2.0, 0.5])
+    g = np.array([3.0, -0.01, 1e-3])
+    m = v = np.zeros(3)
+    w1, m, v = PO.adam(w, g, m, v, 1, lr=0.01)
+    assert np.allclose(w1, w - 0.01 * np.sign(g), rtol=0, atol=1e-7)
+    # a constant gradient keeps the bias-corrected ratio at 1
+    w2, _, _ = PO.adam(w1, g, m, v, 2, lr=0.01)
+    assert np.allclose(w2, w1 - 0.01 * np.sign(g), rtol=0, atol=1e-7)
