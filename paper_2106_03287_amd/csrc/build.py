@@ -13,6 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 SOURCES = [
     (os.path.join(HERE, "stein_icp.hip"), []),
     (os.path.join(HERE, "nn_bf16.hip"), ["-fno-honor-nans", "-mno-amdgpu-ieee"]),
+    (os.path.join(HERE, "proposal.hip"), []),
 ]
 OUT = os.path.join(PKG, "libstein_icp.so")
 

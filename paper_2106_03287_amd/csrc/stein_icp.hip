@@ -788,6 +788,11 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
 
 // ====================================================================== ABI
 
+namespace sicp {
+// Error reporting shared with the other translation units of the library.
+__attribute__((visibility("hidden"))) int report_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace sicp
+
 extern "C" {
 
 void stein_icp_default_config(stein_icp_config* c)

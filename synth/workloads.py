@@ -95,3 +95,26 @@ def batched_problems(n_pairs: int = 64, *, K=None, m=None, T=None,
         out.append(Problem("batched", pair, theta0, sched, K, m, T, w["lr"], seed,
                            {"pair_index": p}))
     return out
+
+
+# ---------------------------------------------------------------------------
+# learned-proposal data: fresh seeded pairs of the cuboid and Kinect shapes
+# ---------------------------------------------------------------------------
+
+PROPOSAL_TRAIN_SEED = 5_000_000
+PROPOSAL_TEST_SEED = 6_000_000
+
+
+def proposal_pair_spec(split: str, i: int) -> tuple[str, int]:
+    """(generator, seed) of pair i of the proposal's training or test split:
+    even i cuboid, odd i Kinect-shaped, seeds disjoint from the benchmark
+    workloads and between the splits."""
+    base = {"train": PROPOSAL_TRAIN_SEED, "test": PROPOSAL_TEST_SEED}[split]
+    return ("cuboid" if i % 2 == 0 else "kinect"), base + i
+
+
+def generate_pair(spec: tuple[str, int]) -> tuple[str, int, Pair]:
+    """Build one pair from a (generator, seed) spec (picklable, for worker
+    processes)."""
+    kind, seed = spec
+    return kind, seed, _generate(kind, seed)
