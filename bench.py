@@ -70,6 +70,17 @@ def cpu_baseline(prob, budget_s=15.0):
                       f"m={prob.m}, M={len(prob.pair.ref)}), FP64 oracle with OpenMP NN"}
 
 
+# NN shapes (queries per lane, wavefronts per workgroup, chunk, persistent
+# workgroups per CU) pinned from a sweep of the tuner's space on one MI355X
+# (full solves, median of 3); the runner-up shapes are within 2 %
+PINNED_TILING = {
+    ("kinect", "fp32"): "4,16,2048,2",
+    ("kinect", "bf16"): "2,8,20096,0",
+    ("lidar", "fp32"): "4,8,4096,0",
+    ("lidar", "bf16"): "1,8,25088,0",
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,7 +91,8 @@ def main():
     ap.add_argument("--nn", default="fp32", choices=["fp32", "bf16"],
                     help="nearest-neighbour search: exact FP32, or BF16 matrix-core screen + FP32 rerank")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="tune the NN shape at init instead of using the pinned shape of the workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--iters", type=int, default=0,
@@ -97,6 +109,10 @@ def main():
     import synth
     from paper_2106_03287_amd import stein_icp as S
 
+    if not args.tiling and not args.autotune:
+        args.tiling = PINNED_TILING.get((args.workload, args.nn), "")
+        if not args.tiling:
+            args.autotune = 1
     if args.workload == "batched":
         return run_batched(args)
     if args.workload == "proposal":

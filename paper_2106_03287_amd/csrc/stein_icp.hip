@@ -536,7 +536,7 @@ int autotune(stein_icp_ctx* c, hipStream_t s)
                 if (rc) return rc;
                 HIP_TRY(enqueue_stage(c, 0, s));  // warm-up
                 HIP_TRY(enqueue_stage(c, 1, s));
-                const int reps = 5;
+                const int reps = 10;
                 HIP_TRY(hipEventRecord(e0, s));
                 for (int r = 0; r < reps; ++r) {
                     HIP_TRY(enqueue_stage(c, 0, s));
@@ -560,7 +560,7 @@ int autotune(stein_icp_ctx* c, hipStream_t s)
         if (rc) return rc;
         HIP_TRY(enqueue_stage(c, 0, s));
         HIP_TRY(enqueue_stage(c, 1, s));
-        const int reps = 5;
+        const int reps = 10;
         HIP_TRY(hipEventRecord(e0, s));
         for (int r = 0; r < reps; ++r) {
             HIP_TRY(enqueue_stage(c, 0, s));
