@@ -141,9 +141,13 @@ struct stein_icp_ctx {
     float4* src4 = nullptr;
     float4* ref4 = nullptr;
     int32_t* sched = nullptr;
+    // theta / step are the current particles and step counts, theta_next /
+    // step_next what the coming update writes; the two swap after every
+    // iteration (parity 0: the first of each pair of buffers is current)
     double *theta = nullptr, *theta_next = nullptr, *mom = nullptr, *vel = nullptr, *gbar = nullptr, *phi = nullptr;
     double* h = nullptr;
-    int64_t* step = nullptr;
+    int64_t *step = nullptr, *step_next = nullptr;
+    int parity = 0;
     Pose* pose = nullptr;
     float4* queries = nullptr;   // FP32 queries of the coming iteration, K*m per pair
     uint4* apack = nullptr;      // BF16 reference fragments (BF16 screen only)
@@ -157,7 +161,7 @@ struct stein_icp_ctx {
     hipStream_t cap_stream = nullptr;   // graph capture
     hipStream_t side_stream = nullptr;  // bandwidth branch of a captured iteration
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    std::map<int, hipGraphExec_t> graphs;
+    std::map<int, hipGraphExec_t> graphs;   // key 2 * iterations + starting parity
 };
 
 namespace {
@@ -340,6 +344,7 @@ SvgdArgs svgd_args(const stein_icp_ctx* c)
     v.mom = c->mom;
     v.vel = c->vel;
     v.step = c->step;
+    v.step_next = c->step_next;
     v.gbar = c->gbar;
     v.phi = c->phi;
     v.h = c->h;
@@ -364,7 +369,7 @@ hipError_t enqueue_queries(const stein_icp_ctx* c, hipStream_t s)
 }
 
 // Stage 0: nearest neighbours, 1: gradients, 2: bandwidths, 3: Stein
-// direction, update and commit.
+// direction and update (into theta_next / step_next).
 hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
 {
     if (stage == 0) {
@@ -405,10 +410,17 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
         return hipGetLastError();
     }
     hipLaunchKernelGGL(svgd_phi_update_kernel, dim3((unsigned)ceil_div(c->K, 4), (unsigned)c->P), dim3(256), 0, s, v);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(svgd_finish_kernel, dim3((unsigned)c->P), dim3(256), 0, s, v);
     return hipGetLastError();
+}
+
+// After n enqueued iterations the buffers the updates wrote are current.
+void advance(stein_icp_ctx* c, int64_t n)
+{
+    if (n & 1) {
+        std::swap(c->theta, c->theta_next);
+        std::swap(c->step, c->step_next);
+        c->parity ^= 1;
+    }
 }
 
 constexpr int kStages = 4;  // nearest neighbours, gradients, bandwidths, direction + update
@@ -439,9 +451,12 @@ hipError_t enqueue_iteration_forked(const stein_icp_ctx* c, hipStream_t s)
     return e;
 }
 
+// Graph of `len` iterations starting from the context's current parity
+// (the kernels' buffer arguments are fixed at capture).
 int get_graph(stein_icp_ctx* c, int len, hipGraphExec_t* out)
 {
-    auto it = c->graphs.find(len);
+    const int key = 2 * len + c->parity;
+    auto it = c->graphs.find(key);
     if (it != c->graphs.end()) {
         *out = it->second;
         return STEIN_ICP_OK;
@@ -452,7 +467,21 @@ int get_graph(stein_icp_ctx* c, int len, hipGraphExec_t* out)
     if (!c->ev_join) HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int i = 0; i < len && e == hipSuccess; ++i) e = enqueue_iteration_forked(c, c->cap_stream);
+    // the capture walks the buffers forward; the launch advances them for real
+    double* const th0 = c->theta;
+    double* const th1 = c->theta_next;
+    int64_t* const st0 = c->step;
+    int64_t* const st1 = c->step_next;
+    const int par = c->parity;
+    for (int i = 0; i < len && e == hipSuccess; ++i) {
+        e = enqueue_iteration_forked(c, c->cap_stream);
+        advance(c, 1);
+    }
+    c->theta = th0;
+    c->theta_next = th1;
+    c->step = st0;
+    c->step_next = st1;
+    c->parity = par;
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -464,7 +493,7 @@ int get_graph(stein_icp_ctx* c, int len, hipGraphExec_t* out)
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(STEIN_ICP_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    c->graphs[len] = ex;
+    c->graphs[key] = ex;
     *out = ex;
     return STEIN_ICP_OK;
 }
@@ -476,7 +505,10 @@ int run_iters(stein_icp_ctx* c, int32_t n, hipStream_t s)
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(s, &st));
     if (!c->cfg.use_graph || st != hipStreamCaptureStatusNone) {
-        for (int32_t i = 0; i < n; ++i) HIP_TRY(enqueue_iteration(c, s));
+        for (int32_t i = 0; i < n; ++i) {
+            HIP_TRY(enqueue_iteration(c, s));
+            advance(c, 1);
+        }
         return STEIN_ICP_OK;
     }
     int32_t left = n;
@@ -486,6 +518,7 @@ int run_iters(stein_icp_ctx* c, int32_t n, hipStream_t s)
         int rc = get_graph(c, len, &ex);
         if (rc) return rc;
         HIP_TRY(hipGraphLaunch(ex, s));
+        advance(c, len);
         left -= len;
     }
     return STEIN_ICP_OK;
@@ -687,7 +720,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     const size_t o_theta = take(8 * PK6), o_thn = take(8 * PK6), o_mom = take(8 * PK6), o_vel = take(8 * PK6);
     const size_t o_gbar = take(8 * PK6), o_phi = take(8 * PK6);
     const size_t o_h = take(8 * 2 * (size_t)P);
-    const size_t o_step = take(8 * (size_t)P);
+    const size_t o_step = take(8 * (size_t)P), o_stepn = take(8 * (size_t)P);
     const size_t o_pose = take(sizeof(Pose) * (size_t)P * K);
     const size_t o_queries = take(sizeof(float4) * (size_t)P * nq);
     const size_t o_apack = take(sizeof(uint4) * (size_t)std::max<int64_t>(apack_n, 1));
@@ -711,6 +744,8 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     c->phi = (double*)(c->arena + o_phi);
     c->h = (double*)(c->arena + o_h);
     c->step = (int64_t*)(c->arena + o_step);
+    c->step_next = (int64_t*)(c->arena + o_stepn);
+    c->parity = 0;
     c->pose = (Pose*)(c->arena + o_pose);
     c->queries = (float4*)(c->arena + o_queries);
     c->apack = (uint4*)(c->arena + o_apack);
@@ -971,6 +1006,7 @@ int stein_icp_stage_times(stein_icp_ctx* ctx, int32_t n_iters, double* ms_out, v
             if (err == hipSuccess) err = hipEventRecord(e[st + 1], s);
         }
         if (err != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, std::string("profiled step: ") + hipGetErrorString(err));
+        else advance(ctx, 1);
     }
     if (rc == STEIN_ICP_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, "sync failed");
     double t[kStages] = {0, 0, 0, 0};

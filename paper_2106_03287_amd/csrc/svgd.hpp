@@ -1,6 +1,6 @@
 // Stein direction (Eq. 16) and particle update (Eq. 12 with Adam).
 //
-// Three kernels per iteration:
+// Two kernels per iteration:
 //  * svgd_bandwidth_kernel, one 1024-thread workgroup per (pair, block):
 //    block 0 the translation kernel, block 1 the wrapped-angle rotation
 //    kernel of Eq. 17. The median heuristic h = med^2 / ln K needs the middle
@@ -17,10 +17,10 @@
 //    phi_k = (1/K) sum_l [G_l k(l,k) + grad_{theta_l} k(l,k)] with
 //    G_l = -N gbar_l + grad log p(theta_l) (Eq. 10 with Eqs. 14-15), lanes over
 //    l and a fixed-shape shuffle reduction; then Adam on -phi (or
-//    theta += lr phi) for particle k, written to a second buffer (other
-//    wavefronts still read the current particles), the particle's next pose
-//    and its FP32 queries of the next iteration.
-//  * svgd_finish_kernel: commits the new particles and advances the step.
+//    theta += lr phi) for particle k, written to the other particle buffer
+//    (other wavefronts still read the current particles; the buffers swap
+//    roles every iteration), the particle's next pose and its FP32 queries
+//    of the next iteration, and the pair's next step count.
 #pragma once
 
 #include "common.hpp"
@@ -40,10 +40,11 @@ struct SvgdParams {
 struct SvgdArgs {
     const PairDesc* pairs;
     double* theta;        // current particles, K x 6 per pair
-    double* theta_next;   // updated particles before the commit
+    double* theta_next;   // particles after this iteration's update (the buffers alternate)
     double* mom;
     double* vel;
-    int64_t* step;
+    int64_t* step;        // completed updates per pair
+    int64_t* step_next;   // step + 1, written by the update
     const double* gbar;
     double* phi;
     double* h;            // 2 per pair
@@ -572,6 +573,7 @@ __global__ __launch_bounds__(256) void svgd_phi_update_kernel(SvgdArgs a)
     Pose P;
     pose_from_theta(tn, &P);
     if (lane == 0) a.pose[p * K + k] = P;
+    if (k == 0 && lane == 0) a.step_next[p] = a.step[p] + 1;   // read only by the next iteration
     const int64_t row = (a.step[p] + 1) % a.rows;
     const int32_t* __restrict__ srow = a.sched + pd.sched_off + row * a.m;
     for (int i0 = lane; i0 < a.m; i0 += 4 * kWave) {
@@ -585,15 +587,6 @@ __global__ __launch_bounds__(256) void svgd_phi_update_kernel(SvgdArgs a)
         for (int u = 0; u < 4; ++u)
             if (i0 + u * kWave < a.m) a.queries[pd.q_off + (int64_t)k * a.m + i0 + u * kWave] = make_query(&P, sp[u]);
     }
-}
-
-// grid pairs: commit the new particles and advance the step count.
-__global__ void svgd_finish_kernel(SvgdArgs a)
-{
-    const int64_t p = blockIdx.x;
-    for (int e = threadIdx.x; e < 6 * a.K; e += blockDim.x)
-        a.theta[p * a.K * 6 + e] = a.theta_next[p * a.K * 6 + e];
-    if (threadIdx.x == 0) a.step[p] += 1;
 }
 
 }  // namespace sicp
