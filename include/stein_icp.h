@@ -173,12 +173,11 @@ int stein_icp_set_nn_tiling(stein_icp_ctx *ctx, int32_t queries_per_lane, int32_
                             int32_t chunk, int32_t persist, void *hip_stream);
 
 /* Profiled mode: run n_iters >= 1 iterations with plain launches (no graph),
- * recording HIP events on `hip_stream` around each stage, and return the
- * summed stage times in ms_out[4] (host): nearest neighbours (Eq. 1), mean
- * gradients (Eqs. 4-5), median-heuristic bandwidths (Sec. V), Stein direction
- * plus update (Eqs. 12, 16). Stages run one after another here; a captured
- * graph overlaps the bandwidths with the first two. Advances the state like
- * stein_icp_step. Blocking. */
+ * recording HIP events on `hip_stream` around each launch, and return the
+ * summed times in ms_out[3] (host): nearest neighbours (Eq. 1); mean
+ * gradients (Eqs. 4-5) together with the median-heuristic bandwidths
+ * (Sec. V), which share one launch; Stein direction plus update (Eqs. 12,
+ * 16). Advances the state like stein_icp_step. Blocking. */
 int stein_icp_stage_times(stein_icp_ctx *ctx, int32_t n_iters, double *ms_out, void *hip_stream);
 
 /* Mean duration in ms of the nearest-neighbour kernel (Eq. 1) over

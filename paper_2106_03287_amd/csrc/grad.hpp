@@ -1,13 +1,14 @@
 // Per-particle mean point-to-point gradient (Eqs. 4-5), fused with the final
 // reduction of the per-chunk nearest-neighbour keys.
 //
-// One workgroup per particle. Each thread takes minibatch points i = tid,
-// tid + 256, ...: it reduces the chunk keys of its query and resolves the
+// One group of 256 threads per particle, four groups to a workgroup. Each
+// thread takes minibatch points i = t, t + 256, ...: it reduces the chunk
+// keys of its query and resolves the
 // winning tile to the matched reference index, recomputes the FP64
 // transform s' = R s + u, forms the
 // residual e = s' - r and the six contributions e and e^T (dR/dtheta_d) s,
-// accumulating in FP64. The 256 partial sums are combined by a fixed-shape
-// tree in LDS, so the result does not depend on scheduling.
+// accumulating in FP64. The group's 256 partial sums are combined by a
+// fixed-shape tree in LDS, so the result does not depend on scheduling.
 #pragma once
 
 #include "common.hpp"
@@ -29,55 +30,66 @@ struct GradArgs {
     int32_t K, m, rows, pad_;
 };
 
-__global__ __launch_bounds__(kGradThreads) void grad_kernel(GradArgs a)
-{
-    const int64_t pk = blockIdx.x;
-    const int64_t p = pk / a.K;
-    const int64_t k = pk - p * a.K;
-    const PairDesc pd = a.pairs[p];
-    const int64_t nq = (int64_t)a.K * a.m;
-    const int64_t row = a.step[p] % a.rows;
-    const Pose* __restrict__ P = a.pose + pk;
+constexpr int kGradGroups = 4;   // particles per 1024-thread workgroup, kGradThreads threads each
 
+// Gradient of particle pk (global index over pairs, pk < nparticles) by the
+// group `grp` of kGradThreads threads (lt = thread within the group); red is
+// the workgroup's 6 x (kGradGroups kGradThreads) FP64 LDS tree. Every thread
+// of the workgroup takes part in the tree's barriers, also for pk >= n.
+__device__ __forceinline__ void grad_group(const GradArgs& a, int64_t pk, int64_t n, int grp, int lt, double* red)
+{
+    constexpr int W = kGradGroups * kGradThreads;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < a.m; i += kGradThreads) {
-        const int64_t qi = k * a.m + i;
-        const uint64_t key = min_chunk_keys(a.partial + pd.part_off + qi, pd.chunks, nq);
-        const int32_t j = resolve_key(key, a.queries[pd.q_off + qi], a.ref4 + pd.ref_off, pd.n_ref_pad);
-        a.match[p * nq + qi] = j;
-        const float4 s = a.src4[pd.src_off + a.sched[pd.sched_off + row * a.m + i]];
-        const float4 r = a.ref4[pd.ref_off + j];
-        double q[3];
-        transform_f64(P->R, P->u, s.x, s.y, s.z, q);
-        {
+    const bool live = pk < n;
+    int64_t p = 0, k = 0;
+    if (live) {
+        p = pk / a.K;
+        k = pk - p * a.K;
+        const PairDesc pd = a.pairs[p];
+        const int64_t nq = (int64_t)a.K * a.m;
+        const int64_t row = a.step[p] % a.rows;
+        const Pose* __restrict__ P = a.pose + pk;
+        for (int i = lt; i < a.m; i += kGradThreads) {
+            const int64_t qi = k * a.m + i;
+            const uint64_t key = min_chunk_keys(a.partial + pd.part_off + qi, pd.chunks, nq);
+            const int32_t j = resolve_key(key, a.queries[pd.q_off + qi], a.ref4 + pd.ref_off, pd.n_ref_pad);
+            a.match[p * nq + qi] = j;
+            const float4 s = a.src4[pd.src_off + a.sched[pd.sched_off + row * a.m + i]];
+            const float4 r = a.ref4[pd.ref_off + j];
+            double q[3];
+            transform_f64(P->R, P->u, s.x, s.y, s.z, q);
+            {
 #pragma clang fp contract(off)
-            const double e0 = q[0] - (double)r.x, e1 = q[1] - (double)r.y, e2 = q[2] - (double)r.z;
-            acc[0] += e0;
-            acc[1] += e1;
-            acc[2] += e2;
+                const double e0 = q[0] - (double)r.x, e1 = q[1] - (double)r.y, e2 = q[2] - (double)r.z;
+                acc[0] += e0;
+                acc[1] += e1;
+                acc[2] += e2;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double* D = P->dR + 9 * d;
-                const double v0 = (D[0] * s.x + D[1] * s.y) + D[2] * s.z;
-                const double v1 = (D[3] * s.x + D[4] * s.y) + D[5] * s.z;
-                const double v2 = (D[6] * s.x + D[7] * s.y) + D[8] * s.z;
-                acc[3 + d] += (e0 * v0 + e1 * v1) + e2 * v2;
+                for (int d = 0; d < 3; ++d) {
+                    // compiler barrier (no instruction): load each 3 x 3 block of
+                    // dR where it is used instead of keeping all 27 in registers
+                    asm volatile("" ::: "memory");
+                    const double* D = P->dR + 9 * d;
+                    const double v0 = (D[0] * s.x + D[1] * s.y) + D[2] * s.z;
+                    const double v1 = (D[3] * s.x + D[4] * s.y) + D[5] * s.z;
+                    const double v2 = (D[6] * s.x + D[7] * s.y) + D[8] * s.z;
+                    acc[3 + d] += (e0 * v0 + e1 * v1) + e2 * v2;
+                }
             }
         }
     }
-
-    __shared__ double red[6][kGradThreads];
+    double* r0 = red + grp * kGradThreads;
 #pragma unroll
-    for (int d = 0; d < 6; ++d) red[d][threadIdx.x] = acc[d];
+    for (int d = 0; d < 6; ++d) r0[d * W + lt] = acc[d];
     __syncthreads();
     for (int w = kGradThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
+        if (lt < w) {
 #pragma unroll
-            for (int d = 0; d < 6; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + w];
+            for (int d = 0; d < 6; ++d) r0[d * W + lt] += r0[d * W + lt + w];
         }
         __syncthreads();
     }
-    if (threadIdx.x < 6) a.gbar[pk * 6 + threadIdx.x] = red[threadIdx.x][0] / (double)a.m;
+    if (live && lt < 6) a.gbar[pk * 6 + lt] = r0[lt * W] / (double)a.m;
 }
 
 }  // namespace sicp

@@ -14,7 +14,7 @@
 #include "stein_icp.h"
 
 #include "common.hpp"
-#include "grad.hpp"
+#include "grad_bw.hpp"
 #include "nn.hpp"
 #include "nn_bf16_launch.h"
 #include "prep.hpp"
@@ -159,8 +159,6 @@ struct stein_icp_ctx {
     uint64_t* partial = nullptr;
 
     hipStream_t cap_stream = nullptr;   // graph capture
-    hipStream_t side_stream = nullptr;  // bandwidth branch of a captured iteration
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::map<int, hipGraphExec_t> graphs;   // key 2 * iterations + starting parity
 };
 
@@ -368,8 +366,8 @@ hipError_t enqueue_queries(const stein_icp_ctx* c, hipStream_t s)
     return hipGetLastError();
 }
 
-// Stage 0: nearest neighbours, 1: gradients, 2: bandwidths, 3: Stein
-// direction and update (into theta_next / step_next).
+// Stage 0: nearest neighbours, 1: gradients and bandwidths (one launch),
+// 2: Stein direction and update (into theta_next / step_next).
 hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
 {
     if (stage == 0) {
@@ -400,15 +398,12 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
     g.K = c->K;
     g.m = c->m;
     g.rows = c->rows;
-    hipLaunchKernelGGL(grad_kernel, dim3((unsigned)((int64_t)c->P * c->K)), dim3(kGradThreads), 0, s, g);
+    const int64_t blocks = 2 * (int64_t)c->P + ceil_div((int64_t)c->P * c->K, kGradGroups);
+    hipLaunchKernelGGL(grad_bandwidth_kernel, dim3((unsigned)blocks), dim3(kSvgdThreads), grad_bw_lds_bytes(c->K), s,
+                       g, svgd_args(c), c->P);
     return hipGetLastError();
     }
     const SvgdArgs v = svgd_args(c);
-    if (stage == 2) {
-        hipLaunchKernelGGL(svgd_bandwidth_kernel, dim3((unsigned)c->P, 2), dim3(kSvgdThreads),
-                           bandwidth_lds_bytes(c->K), s, v);
-        return hipGetLastError();
-    }
     hipLaunchKernelGGL(svgd_phi_update_kernel, dim3((unsigned)ceil_div(c->K, 4), (unsigned)c->P), dim3(256), 0, s, v);
     return hipGetLastError();
 }
@@ -423,7 +418,7 @@ void advance(stein_icp_ctx* c, int64_t n)
     }
 }
 
-constexpr int kStages = 4;  // nearest neighbours, gradients, bandwidths, direction + update
+constexpr int kStages = 3;  // nearest neighbours, gradients + bandwidths, direction + update
 
 // One iteration in stream order on `s`.
 hipError_t enqueue_iteration(const stein_icp_ctx* c, hipStream_t s)
@@ -433,22 +428,6 @@ hipError_t enqueue_iteration(const stein_icp_ctx* c, hipStream_t s)
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
-}
-
-// One iteration for graph capture: the bandwidths depend only on the current
-// particles, so they run on a forked branch beside the nearest-neighbour and
-// gradient kernels and join before the direction + update.
-hipError_t enqueue_iteration_forked(const stein_icp_ctx* c, hipStream_t s)
-{
-    hipError_t e = hipEventRecord(c->ev_fork, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(c->side_stream, c->ev_fork, 0);
-    if (e == hipSuccess) e = enqueue_stage(c, 2, c->side_stream);
-    if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->side_stream);
-    if (e == hipSuccess) e = enqueue_stage(c, 0, s);
-    if (e == hipSuccess) e = enqueue_stage(c, 1, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_join, 0);
-    if (e == hipSuccess) e = enqueue_stage(c, 3, s);
-    return e;
 }
 
 // Graph of `len` iterations starting from the context's current parity
@@ -462,9 +441,6 @@ int get_graph(stein_icp_ctx* c, int len, hipGraphExec_t* out)
         return STEIN_ICP_OK;
     }
     if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    if (!c->side_stream) HIP_TRY(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
-    if (!c->ev_fork) HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-    if (!c->ev_join) HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     // the capture walks the buffers forward; the launch advances them for real
@@ -474,7 +450,7 @@ int get_graph(stein_icp_ctx* c, int len, hipGraphExec_t* out)
     int64_t* const st1 = c->step_next;
     const int par = c->parity;
     for (int i = 0; i < len && e == hipSuccess; ++i) {
-        e = enqueue_iteration_forked(c, c->cap_stream);
+        e = enqueue_iteration(c, c->cap_stream);
         advance(c, 1);
     }
     c->theta = th0;
@@ -622,9 +598,6 @@ void free_ctx(stein_icp_ctx* c)
     (void)hipDeviceSynchronize();
     for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->arena) (void)hipFree(c->arena);
     if (c->d_work) (void)hipFree(c->d_work);
     if (c->partial) (void)hipFree(c->partial);
@@ -684,8 +657,14 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     }
     c->tiling = default_tiling(c->pairs, nq);
     if (cfg->nn_mode == STEIN_ICP_NN_BF16_RERANK && c->tiling.q > 2) c->tiling.q = 2;
-    HIP_TRY(hipFuncSetAttribute((const void*)svgd_bandwidth_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)bandwidth_lds_bytes(K)));
+    {
+        // the attribute is a per-kernel ceiling shared by every context: use
+        // the largest any particle count needs (the launch sizes the rest)
+        size_t most = 0;
+        for (int k = 1; k <= kMaxK; ++k) most = std::max(most, grad_bw_lds_bytes(k));
+        HIP_TRY(hipFuncSetAttribute((const void*)grad_bandwidth_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)most));
+    }
     const bool bf16 = cfg->nn_mode == STEIN_ICP_NN_BF16_RERANK;
     int64_t apack_n = 0;
     if (bf16) {
@@ -1009,7 +988,7 @@ int stein_icp_stage_times(stein_icp_ctx* ctx, int32_t n_iters, double* ms_out, v
         else advance(ctx, 1);
     }
     if (rc == STEIN_ICP_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, "sync failed");
-    double t[kStages] = {0, 0, 0, 0};
+    double t[kStages] = {0, 0, 0};
     for (int32_t i = 0; i < n_iters && rc == STEIN_ICP_OK; ++i)
         for (int k = 0; k < kStages; ++k) {
             float ms = 0.f;

@@ -1,7 +1,8 @@
 // Stein direction (Eq. 16) and particle update (Eq. 12 with Adam).
 //
-// Two kernels per iteration:
-//  * svgd_bandwidth_kernel, one 1024-thread workgroup per (pair, block):
+// Per iteration:
+//  * bandwidth_body, one 1024-thread workgroup per (pair, block), run by
+//    the workgroups of the gradient launch that carry no particles:
 //    block 0 the translation kernel, block 1 the wrapped-angle rotation
 //    kernel of Eq. 17. The median heuristic h = med^2 / ln K needs the middle
 //    order statistics of the K(K-1)/2 distances between distinct particles,
@@ -10,9 +11,8 @@
 //    narrows them to one bin in at most two rounds, and the exact FP64
 //    distances of that bin's few pairs are recomputed and ranked by counting.
 //    Larger K keep FP64 distances in global memory and bin by value. A radix
-//    select over IEEE-754 bit patterns covers the degenerate cases. The
-//    kernel depends only on the particles, so it runs beside the
-//    nearest-neighbour stage.
+//    select over IEEE-754 bit patterns covers the degenerate cases. It
+//    depends only on the particles, so it runs beside the gradients.
 //  * svgd_phi_update_kernel, one wavefront per particle k:
 //    phi_k = (1/K) sum_l [G_l k(l,k) + grad_{theta_l} k(l,k)] with
 //    G_l = -N gbar_l + grad log p(theta_l) (Eq. 10 with Eqs. 14-15), lanes over
@@ -326,6 +326,7 @@ __device__ __forceinline__ double block_select(const Src& src, int64_t r, Select
             for (uint32_t t = tid; t < c; t += kSvgdThreads) {
                 const double x = sh.cand[t];
                 uint32_t less = 0, leq = 0;
+#pragma unroll 8
                 for (uint32_t j = 0; j < c; ++j) {
                     const double y = sh.cand[j];
                     less += y < x;
@@ -380,23 +381,46 @@ __device__ inline double select_keyed(const uint16_t* key, int64_t n, int64_t r,
                 sh.found = 0;
             }
             __syncthreads();
-            for (int64_t q = tid; q < n; q += kSvgdThreads) {
-                const uint32_t x = key[q];
-                if (x >= nlo && x <= nhi) {
-                    const uint32_t slot = atomicAdd(&sh.ncand, 1u);
-                    if (slot < kCandCap) sh.cand[slot] = pair_dist(q, K, rot, th);
+            // walk the triangle as the keys were written (wavefront per row k,
+            // lanes over l), so a taken key's pair needs no index inversion
+            const int lane = tid & (kWave - 1);
+            for (int k = tid >> 6; k < K; k += kSvgdWaves) {
+                const int64_t row = tri_row(k, K);
+                for (int l = k + 1 + lane; l < K; l += kWave) {
+                    const uint32_t x = key[row + (l - k - 1)];
+                    if (x >= nlo && x <= nhi) {
+                        const uint32_t slot = atomicAdd(&sh.ncand, 1u);
+                        if (slot < kCandCap)
+                            sh.cand[slot] = rot ? dist2_rot(th + 6 * k, th + 6 * l) : dist2_trans(th + 6 * k, th + 6 * l);
+                    }
                 }
             }
             __syncthreads();
             const uint32_t c = min(sh.ncand, (uint32_t)kCandCap);
-            for (uint32_t t = tid; t < c; t += kSvgdThreads) {
-                const double x = sh.cand[t];
+            // rank every candidate among all: candidate i and j range g of
+            // G = 1024 / c ranges per thread, counts added in the histogram's
+            // (no longer needed) slots
+            for (uint32_t i = tid; i < 2 * c; i += kSvgdThreads) sh.hist[i] = 0;
+            __syncthreads();
+            const uint32_t G = c ? (uint32_t)kSvgdThreads / c : 1u;
+            if ((uint32_t)tid < c * G) {
+                const uint32_t i = tid % c, g = tid / c;
+                const uint32_t j0 = c * g / G, j1 = c * (g + 1) / G;
+                const double x = sh.cand[i];
                 uint32_t less = 0, leq = 0;
-                for (uint32_t j = 0; j < c; ++j) {
+#pragma unroll 8
+                for (uint32_t j = j0; j < j1; ++j) {
                     const double y = sh.cand[j];
                     less += y < x;
                     leq += y <= x;
                 }
+                if (less) atomicAdd(&sh.hist[i], less);
+                if (leq) atomicAdd(&sh.hist[c + i], leq);
+            }
+            __syncthreads();
+            for (uint32_t t = tid; t < c; t += kSvgdThreads) {
+                const double x = sh.cand[t];
+                const uint32_t less = sh.hist[t], leq = sh.hist[c + t];
                 if ((int64_t)less <= r && r < (int64_t)leq) sh.dres = x;   // same value for all writers
                 if (want_next && (int64_t)less <= r + 1 && r + 1 < (int64_t)leq) {
                     sh.wmax[0] = x;
@@ -423,18 +447,17 @@ constexpr int64_t kMaxKeyedPairs = 60000;
 
 // grid (pairs, 2), 1024 threads. blockIdx.y: 0 translation, 1 rotation.
 // Dynamic LDS: K x 6 particles (FP64) followed by the 16-bit pair keys.
-__global__ __launch_bounds__(kSvgdThreads) void svgd_bandwidth_kernel(SvgdArgs a)
+// Median-heuristic bandwidth of pair p, block rot (0 translation, 1
+// rotation), by one 1024-thread workgroup; `sh` and `dyn`
+// (bandwidth_lds_bytes(K)) are the workgroup's LDS.
+__device__ __forceinline__ void bandwidth_body(const SvgdArgs& a, int64_t p, int rot, SelectShared& sh, double* dyn)
 {
-    extern __shared__ double dyn[];
-    const int64_t p = blockIdx.x;
-    const int rot = blockIdx.y;
     const int K = a.K;
     const int tid = threadIdx.x;
     if (a.prm.bandwidth == 1 || K < 2) {
         if (tid == 0) a.h[2 * p + rot] = a.prm.bandwidth == 1 ? (rot ? a.prm.h_fixed_r : a.prm.h_fixed_t) : 1.0;
         return;
     }
-    __shared__ SelectShared sh;
     double* th = dyn;
     for (int e = tid; e < 6 * K; e += kSvgdThreads) th[e] = a.theta[p * K * 6 + e];
     __syncthreads();
@@ -477,7 +500,7 @@ __global__ __launch_bounds__(kSvgdThreads) void svgd_bandwidth_kernel(SvgdArgs a
     }
 }
 
-// Dynamic LDS bytes of svgd_bandwidth_kernel.
+// LDS bytes of bandwidth_body besides SelectShared.
 inline size_t bandwidth_lds_bytes(int K)
 {
     const int64_t np = (int64_t)K * (K - 1) / 2;

@@ -275,10 +275,10 @@ def stein_icp_set_nn_tiling(ctx, queries_per_lane, waves, chunk, persist=0, stre
 
 def stein_icp_stage_times(ctx, n_iters, stream=None):
     """Summed ms per stage over n_iters profiled iterations."""
-    out = (C.c_double * 4)()
+    out = (C.c_double * 3)()
     _check("stein_icp_stage_times", lib().stein_icp_stage_times(ctx, int(n_iters), out,
                                                                 _stream(stream)))
-    return {"nn": out[0], "grad": out[1], "bandwidth": out[2], "phi_update": out[3]}
+    return {"nn": out[0], "grad_bandwidth": out[1], "phi_update": out[2]}
 
 
 def stein_icp_time_nn(ctx, n_launches, stream=None):
