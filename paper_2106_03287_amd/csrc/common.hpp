@@ -11,7 +11,7 @@ constexpr int kTile = 16;            // references per tile of the NN scan
 constexpr float kPadCoord = 1e18f;   // coordinate of padding references
 constexpr int kMaxK = 1024;          // particles per pair (one workgroup)
 constexpr int kSvgdThreads = 1024;   // threads of the per-pair SVGD workgroup
-constexpr int kGradThreads = 256;    // threads of the per-particle gradient workgroup
+constexpr int kGradThreads = 512;    // threads per particle in the gradient launch
 
 // One cloud pair inside a (possibly batched) context. Offsets are in
 // elements of the packed arrays they index.

@@ -1,13 +1,13 @@
 // Per-particle mean point-to-point gradient (Eqs. 4-5), fused with the final
 // reduction of the per-chunk nearest-neighbour keys.
 //
-// One group of 256 threads per particle, four groups to a workgroup. Each
-// thread takes minibatch points i = t, t + 256, ...: it reduces the chunk
+// One group of 512 threads per particle, two groups to a workgroup. Each
+// thread takes minibatch points i = t, t + 512, ...: it reduces the chunk
 // keys of its query and resolves the
 // winning tile to the matched reference index, recomputes the FP64
 // transform s' = R s + u, forms the
 // residual e = s' - r and the six contributions e and e^T (dR/dtheta_d) s,
-// accumulating in FP64. The group's 256 partial sums are combined by a
+// accumulating in FP64. The group's 512 partial sums are combined by a
 // fixed-shape tree in LDS, so the result does not depend on scheduling.
 #pragma once
 
@@ -30,7 +30,7 @@ struct GradArgs {
     int32_t K, m, rows, pad_;
 };
 
-constexpr int kGradGroups = 4;   // particles per 1024-thread workgroup, kGradThreads threads each
+constexpr int kGradGroups = 2;   // particles per 1024-thread workgroup, kGradThreads threads each
 
 // Gradient of particle pk (global index over pairs, pk < nparticles) by the
 // group `grp` of kGradThreads threads (lt = thread within the group); red is

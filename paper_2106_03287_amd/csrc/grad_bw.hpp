@@ -2,7 +2,7 @@
 // depend on nothing but the particles and the matches: the median-heuristic
 // bandwidths (Sec. V) and the mean gradients (Eqs. 4-5). The first 2 P
 // workgroups compute the bandwidths of pair w / 2, block w % 2; the others
-// compute the gradients of four particles each. The roles share one dynamic
+// compute the gradients of two particles each. The roles share one dynamic
 // LDS buffer of grad_bw_lds_bytes(K) bytes.
 #pragma once
 
