@@ -74,9 +74,9 @@ int stein_icp_proposal_param_count(int32_t num_particles, int64_t *count);
 
 /* Allocate a model for `cfg` (parameters zero, Adam moments zero, step 0).
  * Blocking. Fails with STEIN_ICP_E_INVALID on a bad config before any
- * device call, STEIN_ICP_E_NOMEM when the buffers do not fit (768 bytes
- * per network input point, 2 max_batch P points, 1792 when P is not a
- * multiple of 64, plus about 1.5 MiB per pair of max_batch). */
+ * device call, STEIN_ICP_E_NOMEM when the buffers do not fit (about 1 MiB
+ * per pair of max_batch; when P is not a multiple of 64 the per-point
+ * activations are kept too, 1792 bytes for each of 2 max_batch P points). */
 int stein_icp_proposal_create(stein_icp_proposal **out, const stein_icp_proposal_config *cfg);
 int stein_icp_proposal_destroy(stein_icp_proposal *model);
 

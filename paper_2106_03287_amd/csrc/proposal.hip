@@ -147,8 +147,8 @@ struct stein_icp_proposal {
     MmdScales scales;
     void* arena = nullptr;
     float *params, *grad, *adam_m, *adam_v;
-    bool fused_pool;   // P % 64 == 0: max-pool folded into the last per-point product
-    float *H1, *H2, *H3;   // H3 only without the fused pool
+    bool fused_pool;       // P % 64 == 0: the fused per-point kernel, no per-point activations in HBM
+    float *H1, *H2, *H3;   // per-point activations, only without the fused kernel
     float *pool_v, *F, *Z, *Y, *dY, *dZ, *dF;
     int32_t *pool_i, *arg, *flags;
     unsigned long long* pool_keys;
@@ -157,6 +157,7 @@ struct stein_icp_proposal {
     int64_t ws_floats, colpart_floats;
     int64_t step = 0;
     int32_t last_batch = 0;   // batch of the last loss call (0: no gradient yet)
+    int32_t num_cus = 256;
 };
 
 namespace {
@@ -201,16 +202,27 @@ int forward(Model* m, hipStream_t s, const float* X, int64_t B)
     const Layout L(m->K);
     const float* w = m->params;
     const int64_t rows = 2 * B * m->P, K6 = 6 * m->K;
-    CHECK(gemm(m, s, 0, 0, rows, kF1, 3, X, 3, w + L.W1, kF1, m->H1, kF1, w + L.b1, 1));
-    CHECK(gemm(m, s, 0, 0, rows, kF2, kF1, m->H1, kF1, w + L.W2, kF2, m->H2, kF2, w + L.b2, 1));
     if (m->fused_pool) {
         fill_u64_kernel<<<(unsigned)ceil_div(2 * B * kF3, 256), 256, 0, s>>>(m->pool_keys, 2 * B * kF3, 0ull);
-        HIP_TRY(hipGetLastError());
-        CHECK(launch_gemm(s, 0, 0, rows, kF3, kF2, m->H2, kF2, w + L.W3, kF3, nullptr, kF3, w + L.b3, 1, 0, 1,
-                          nullptr, m->pool_keys, m->P));
+        MlpArgs ma{};
+        ma.X = X;
+        ma.W1 = w + L.W1;
+        ma.b1 = w + L.b1;
+        ma.W2 = w + L.W2;
+        ma.b2 = w + L.b2;
+        ma.W3 = w + L.W3;
+        ma.b3 = w + L.b3;
+        ma.keys = m->pool_keys;
+        ma.rows = rows;
+        ma.P = m->P;
+        // one workgroup per CU holds the staged weights (LDS bound); tiles are strided over them
+        const int64_t tiles = rows / kMT;
+        mlp_pool_kernel<<<(unsigned)std::min<int64_t>(tiles, m->num_cus), 256, kMlpLdsBytes, s>>>(ma);
         pool_keys_finish_kernel<<<(unsigned)ceil_div(2 * B * kF3, 256), 256, 0, s>>>(m->pool_keys, 2 * B, kF3, m->F,
                                                                                     kFcat, m->arg);
     } else {
+        CHECK(gemm(m, s, 0, 0, rows, kF1, 3, X, 3, w + L.W1, kF1, m->H1, kF1, w + L.b1, 1));
+        CHECK(gemm(m, s, 0, 0, rows, kF2, kF1, m->H1, kF1, w + L.W2, kF2, m->H2, kF2, w + L.b2, 1));
         CHECK(gemm(m, s, 0, 0, rows, kF3, kF2, m->H2, kF2, w + L.W3, kF3, m->H3, kF3, w + L.b3, 1));
         const int64_t nch = ceil_div(m->P, kPoolChunk);
         maxpool_partial_kernel<<<dim3((unsigned)(2 * B), (unsigned)nch), kF3, 0, s>>>(m->H3, m->P, kF3, kPoolChunk,
@@ -242,9 +254,14 @@ int backward(Model* m, hipStream_t s, const float* X, int64_t B)
     CHECK(gemm(m, s, 1, 0, kFcat, kFz, B, m->F, kFcat, m->dZ, kFz, g + L.W4, kFz, nullptr, 0));
     CHECK(colsum(m, s, m->dZ, B, kFz, g + L.b4));
     CHECK(gemm(m, s, 0, 1, B, kFcat, kFz, m->dZ, kFz, w + L.W4, kFz, m->dF, kFcat, nullptr, 0));
-    // slots: gather the winning points' rows and the pooled gradient
-    slot_gather_kernel<<<(unsigned)slots, kF2, 0, s>>>(X, m->H1, m->H2, m->arg, m->F, m->dF, kFcat, m->P, kF1, kF2,
-                                                       kF3, m->G0, m->G1, m->G2, m->val);
+    // slots: gather the winning points' inputs and the pooled gradient, and
+    // recompute their first two layers with the forward's products (one K
+    // slice each, the same MFMA order, bias and ReLU: the same bits)
+    slot_gather_kernel<<<(unsigned)ceil_div(slots, 256), 256, 0, s>>>(X, m->arg, m->F, m->dF, kFcat, m->P, kF3, slots,
+                                                                      m->G0, m->val);
+    HIP_TRY(hipGetLastError());
+    CHECK(launch_gemm(s, 0, 0, slots, kF1, 3, m->G0, 3, w + L.W1, kF1, m->G1, kF1, w + L.b1, 1, 0, 1, nullptr));
+    CHECK(launch_gemm(s, 0, 0, slots, kF2, kF1, m->G1, kF1, w + L.W2, kF2, m->G2, kF2, w + L.b2, 1, 0, 1, nullptr));
     slot_w3_grad_kernel<<<(unsigned)ceil_div((int64_t)kF3 * (kF2 + 1), 256), 256, 0, s>>>(
         m->G2, m->val, 2 * B, kF2, kF3, g + L.W3, g + L.b3);
     slot_da2_kernel<<<(unsigned)ceil_div(slots * kF2, 256), 256, 0, s>>>(m->G2, m->val, w + L.W3, slots, kF2, kF3,
@@ -338,7 +355,7 @@ int stein_icp_proposal_create(stein_icp_proposal** out, const stein_icp_proposal
     };
     const size_t o_params = take(4 * L.total), o_grad = take(4 * L.total), o_m = take(4 * L.total),
                  o_v = take(4 * L.total);
-    const size_t o_H1 = take(4 * rows * kF1), o_H2 = take(4 * rows * kF2);
+    const size_t o_H1 = take(m->fused_pool ? 0 : 4 * rows * kF1), o_H2 = take(m->fused_pool ? 0 : 4 * rows * kF2);
     const size_t o_H3 = take(m->fused_pool ? 0 : 4 * rows * kF3);
     const size_t o_keys = take(8 * slots);
     const size_t o_G0 = take(4 * slots * 3), o_G1 = take(4 * slots * kF1), o_G2 = take(4 * slots * kF2);
@@ -362,8 +379,8 @@ int stein_icp_proposal_create(stein_icp_proposal** out, const stein_icp_proposal
     m->grad = (float*)(a + o_grad);
     m->adam_m = (float*)(a + o_m);
     m->adam_v = (float*)(a + o_v);
-    m->H1 = (float*)(a + o_H1);
-    m->H2 = (float*)(a + o_H2);
+    m->H1 = m->fused_pool ? nullptr : (float*)(a + o_H1);
+    m->H2 = m->fused_pool ? nullptr : (float*)(a + o_H2);
     m->H3 = m->fused_pool ? nullptr : (float*)(a + o_H3);
     m->pool_keys = (unsigned long long*)(a + o_keys);
     m->G0 = (float*)(a + o_G0);
@@ -385,6 +402,16 @@ int stein_icp_proposal_create(stein_icp_proposal** out, const stein_icp_proposal
     m->ws = (float*)(a + o_ws);
     m->colpart = (float*)(a + o_cp);
     m->prep = (float*)(a + o_prep);
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&m->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (m->num_cus < 1) m->num_cus = 256;
+    if (hipFuncSetAttribute((const void*)mlp_pool_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kMlpLdsBytes) != hipSuccess) {
+        (void)hipGetLastError();
+        free_model(m);
+        return fail(STEIN_ICP_E_DEVICE, "cannot give the fused per-point kernel its LDS");
+    }
     if (hipMemset(m->arena, 0, off) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         const hipError_t e = hipGetLastError();
         free_model(m);

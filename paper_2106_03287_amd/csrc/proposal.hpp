@@ -187,6 +187,173 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
             }
 }
 
+// -------------------------------------------------- fused per-point MLP
+// The three per-point layers and the max-pool of one 64-point tile in one
+// workgroup: h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), h3 = relu(h2 W3 +
+// b3), folded into the pool keys as in the pooled GEMM epilogue. Every
+// product is a chain of v_mfma_f32_16x16x32_bf16 over K steps of 32 in
+// increasing order, from zero, with the bias added to the FP32 sum and ReLU
+// after it -- the arithmetic of gemm_bf16_kernel, so a row recomputed by
+// that kernel has the same bits. Activations pass between the layers through
+// LDS as BF16 and never reach HBM. The weights are staged once per workgroup
+// as BF16, column-major with padded rows (the B-operand layout of the GEMM).
+struct MlpArgs {
+    const float* X;   // rows x 3
+    const float *W1, *b1, *W2, *b2, *W3, *b3;
+    unsigned long long* keys;   // clouds x 256
+    int64_t rows, P;            // P % 64 == 0
+};
+
+constexpr int kMT = 64;                 // points per tile
+constexpr int kLd1 = 32 + kLdsPad;      // K stride of x and W1 (K = 3 padded to 32)
+constexpr int kLd2 = 64 + kLdsPad;      // K stride of h1 and W2
+constexpr int kLd3 = 128 + kLdsPad;     // K stride of h2 and W3
+// LDS layout in BF16 elements
+constexpr int kOffW1 = 0;
+constexpr int kOffW2 = kOffW1 + 64 * kLd1;
+constexpr int kOffW3 = kOffW2 + 128 * kLd2;
+constexpr int kOffU = kOffW3 + 256 * kLd3;   // x tile, later h2 tile
+constexpr int kOffH1 = kOffU + kMT * kLd3;
+constexpr int kMlpLdsElems = kOffH1 + kMT * kLd2;
+constexpr size_t kMlpLdsBytes = 2 * (size_t)kMlpLdsElems;
+
+__device__ __forceinline__ bf16x8_t lds_frag(const uint16_t* base, int row, int ld, int k)
+{
+    return __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u16x8_t*>(base + row * ld + k));
+}
+
+__global__ __launch_bounds__(256) void mlp_pool_kernel(MlpArgs g)
+{
+    extern __shared__ __attribute__((aligned(16))) uint16_t sm16[];
+    uint16_t* W1s = sm16 + kOffW1;
+    uint16_t* W2s = sm16 + kOffW2;
+    uint16_t* W3s = sm16 + kOffW3;
+    uint16_t* U = sm16 + kOffU;
+    uint16_t* H1s = sm16 + kOffH1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int fr = lane & 15, fk = 8 * (lane >> 4);
+    // weights, transposed to [column][k] BF16
+    for (int e = tid; e < 64 * 32; e += 256) {
+        const int n = e % 64, k = e / 64;
+        W1s[n * kLd1 + k] = to_bf16(k < 3 ? g.W1[k * 64 + n] : 0.f);
+    }
+    for (int e = tid; e < 128 * 64; e += 256) {
+        const int n = e % 128, k = e / 128;
+        W2s[n * kLd2 + k] = to_bf16(g.W2[k * 128 + n]);
+    }
+    for (int e = tid; e < 256 * 128; e += 256) {
+        const int n = e % 256, k = e / 256;
+        W3s[n * kLd3 + k] = to_bf16(g.W3[k * 256 + n]);
+    }
+    const int64_t ntiles = g.rows / kMT;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t m0 = tile * kMT;
+        const int64_t cloud = m0 / g.P;
+        const int64_t rbase = m0 - cloud * g.P;
+        for (int e = tid; e < kMT * 32; e += 256) {
+            const int r = e / 32, k = e % 32;
+            U[r * kLd1 + k] = to_bf16(k < 3 ? g.X[(m0 + r) * 3 + k] : 0.f);
+        }
+        __syncthreads();   // also orders the weight staging before the first tile
+        // layer 1: wavefront w owns column block w, all four row blocks
+        {
+            const bf16x8_t b = lds_frag(W1s, 16 * wave + fr, kLd1, fk);
+            const int col = 16 * wave + fr;
+            const float bias = g.b1[col];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_frag(U, 16 * rb + fr, kLd1, fk), b, acc, 0, 0, 0);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float v = fmaxf(acc[t] + bias, 0.f);
+                    H1s[(16 * rb + 4 * (lane >> 4) + t) * kLd2 + col] = to_bf16(v);
+                }
+            }
+        }
+        __syncthreads();
+        // layer 2: wavefront w owns column blocks 2w, 2w + 1
+        {
+            f32x4_t acc[4][2];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) acc[rb][c] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                bf16x8_t a[4], b[2];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) a[rb] = lds_frag(H1s, 16 * rb + fr, kLd2, 32 * ks + fk);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) b[c] = lds_frag(W2s, 16 * (2 * wave + c) + fr, kLd2, 32 * ks + fk);
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+                        acc[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[c], acc[rb][c], 0, 0, 0);
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int col = 16 * (2 * wave + c) + fr;
+                const float bias = g.b2[col];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float v = fmaxf(acc[rb][c][t] + bias, 0.f);
+                        U[(16 * rb + 4 * (lane >> 4) + t) * kLd3 + col] = to_bf16(v);   // h2 replaces x
+                    }
+            }
+        }
+        __syncthreads();
+        // layer 3: wavefront w owns column blocks 4w .. 4w + 3; then the
+        // column maxima of the tile's 64 points go to the pool keys
+        {
+            f32x4_t acc[4][4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[rb][c] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                bf16x8_t a[4], b[4];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) a[rb] = lds_frag(U, 16 * rb + fr, kLd3, 32 * ks + fk);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) b[c] = lds_frag(W3s, 16 * (4 * wave + c) + fr, kLd3, 32 * ks + fk);
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        acc[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[c], acc[rb][c], 0, 0, 0);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int col = 16 * (4 * wave + c) + fr;
+                const float bias = g.b3[col];
+                unsigned long long best = 0ull;
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float v = acc[rb][c][t] + bias;
+                        const float r = v > 0.f ? v : 0.f;
+                        const uint32_t row = (uint32_t)(rbase + 16 * rb + 4 * (lane >> 4) + t);
+                        const unsigned long long key =
+                            ((unsigned long long)__float_as_uint(r) << 32) | (unsigned long long)(~row);
+                        best = key > best ? key : best;
+                    }
+                unsigned long long o = __shfl_xor(best, 16);
+                best = o > best ? o : best;
+                o = __shfl_xor(best, 32);
+                best = o > best ? o : best;
+                if (lane < 16) atomicMax(g.keys + cloud * 256 + col, best);
+            }
+        }
+        __syncthreads();   // the next tile overwrites U and H1s
+    }
+}
+
 // C[m][n] (+)= sum_{z < S} W[z][m][n] (+ bias[n]) (ReLU), z in order.
 __global__ void splitk_reduce_kernel(const float* __restrict__ W, int32_t S, int64_t M, int64_t N,
                                      float* __restrict__ C, int64_t ldc, const float* __restrict__ bias,
@@ -269,25 +436,21 @@ __global__ void pool_keys_finish_kernel(const unsigned long long* __restrict__ k
 // layers is linear once the ReLU masks are fixed, so it is taken slot by
 // slot: slot s carries the upstream gradient val_s = dF[c, f] (F[c, f] > 0)
 // on feature f only, and the rows of the layers below it are those of point
-// arg[s]. One workgroup per slot gathers that point's input and activations.
-__global__ void slot_gather_kernel(const float* __restrict__ X, const float* __restrict__ H1,
-                                   const float* __restrict__ H2, const int32_t* __restrict__ arg,
-                                   const float* __restrict__ F, const float* __restrict__ dF, int64_t ld_f,
-                                   int64_t P, int32_t F1, int32_t F2, int32_t F3, float* __restrict__ G0,
-                                   float* __restrict__ G1, float* __restrict__ G2, float* __restrict__ val)
+// arg[s] (recomputed from the gathered input rows by the same products).
+// One thread per slot gathers the point's input and the slot's gradient.
+__global__ void slot_gather_kernel(const float* __restrict__ X, const int32_t* __restrict__ arg,
+                                   const float* __restrict__ F, const float* __restrict__ dF, int64_t ld_f, int64_t P,
+                                   int32_t F3, int64_t slots, float* __restrict__ G0, float* __restrict__ val)
 {
-    const int64_t s = blockIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= slots) return;
     const int64_t c = s / F3, f = s % F3;
     const int64_t row = c * P + min(max(arg[s], 0), (int32_t)(P - 1));   // arg is in range; clamp anyway
-    for (int j = threadIdx.x; j < F2; j += blockDim.x) {
-        if (j < 3) G0[s * 3 + j] = X[row * 3 + j];
-        if (j < F1) G1[s * F1 + j] = H1[row * F1 + j];
-        G2[s * F2 + j] = H2[row * F2 + j];
-    }
-    if (threadIdx.x == 0) {
-        const int64_t e = (c / 2) * ld_f + (c % 2) * F3 + f;
-        val[s] = F[e] > 0.f ? dF[e] : 0.f;
-    }
+    G0[s * 3] = X[row * 3];
+    G0[s * 3 + 1] = X[row * 3 + 1];
+    G0[s * 3 + 2] = X[row * 3 + 2];
+    const int64_t e = (c / 2) * ld_f + (c % 2) * F3 + f;
+    val[s] = F[e] > 0.f ? dF[e] : 0.f;
 }
 
 // dW3[k][f] = sum_c val[c, f] G2[(c, f)][k] and db3[f] = sum_c val[c, f]

@@ -283,3 +283,36 @@ def test_trained_proposal_reaches_plain_300_iteration_quality_in_30_iterations()
         assert prop30 < r["plain_mmd"][100]["mean"]
         assert prop30 < r["plain_mmd"][30]["mean"] / 3
     m.close()
+
+
+@pytest.mark.parametrize("P,B", [(64, 2), (4096, 1)])
+def test_fused_per_point_kernel_matches_the_gemm_chain(P, B):
+    """With P a multiple of 64 the three per-point layers and the max-pool
+    run in one kernel; its result equals the same layers done with the GEMM
+    primitive and a max over points, up to the FP32 reassociation the head's
+    split-K reduction may apply (a different rounding point anywhere in the
+    per-point layers would show as BF16-sized, ~1e-3, differences)."""
+    K = 16
+    params = _params(K, 21)
+    clouds = _clouds(B, P, 22)
+    m = _model(K, P, B, params)
+    y, _ = m.forward(_cuda(clouds))
+    torch.cuda.synchronize()
+    blocks = {k: _cuda(v.astype(np.float32)) for k, v in PO.unpack(params, K).items()}
+    X = _cuda(clouds.reshape(-1, 3))
+    rows = X.shape[0]
+
+    def layer(A, name, n, relu):
+        out = torch.empty(A.shape[0], n, dtype=torch.float32, device="cuda")
+        PR.stein_icp_gemm_bf16(A, blocks["W" + name].reshape(A.shape[1], n).contiguous(), out,
+                               bias=blocks["b" + name], relu=relu)
+        return out
+
+    H3 = layer(layer(layer(X, "1", 64, 1), "2", 128, 1), "3", 256, 1)
+    F = H3.reshape(B * 2, P, 256).amax(dim=1).reshape(B, 512).contiguous()
+    Y = layer(layer(F, "4", 256, 1), "5", 6 * K, 0)
+    torch.cuda.synchronize()
+    got, want = y.cpu().numpy(), Y.cpu().numpy().astype(np.float64).reshape(B, K, 6)
+    assert np.abs(got - want).max() <= 1e-5 * np.abs(want).max()
+    assert rows == 2 * B * P
+    m.close()
