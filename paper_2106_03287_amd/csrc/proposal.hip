@@ -215,9 +215,10 @@ int forward(Model* m, hipStream_t s, const float* X, int64_t B)
         ma.keys = m->pool_keys;
         ma.rows = rows;
         ma.P = m->P;
-        // one workgroup per CU holds the staged weights (LDS bound); tiles are strided over them
+        // one workgroup per CU holds the staged weights (LDS bound) and works
+        // on two tiles at a time; tiles are strided over the workgroups
         const int64_t tiles = rows / kMT;
-        mlp_pool_kernel<<<(unsigned)std::min<int64_t>(tiles, m->num_cus), 256, kMlpLdsBytes, s>>>(ma);
+        mlp_pool_kernel<<<(unsigned)std::min<int64_t>(ceil_div(tiles, 2), m->num_cus), kMlpThreads, kMlpLdsBytes, s>>>(ma);
         pool_keys_finish_kernel<<<(unsigned)ceil_div(2 * B * kF3, 256), 256, 0, s>>>(m->pool_keys, 2 * B, kF3, m->F,
                                                                                     kFcat, m->arg);
     } else {

@@ -212,9 +212,10 @@ constexpr int kLd3 = 128 + kLdsPad;     // K stride of h2 and W3
 constexpr int kOffW1 = 0;
 constexpr int kOffW2 = kOffW1 + 64 * kLd1;
 constexpr int kOffW3 = kOffW2 + 128 * kLd2;
-constexpr int kOffU = kOffW3 + 256 * kLd3;   // x tile, later h2 tile
-constexpr int kOffH1 = kOffU + kMT * kLd3;
-constexpr int kMlpLdsElems = kOffH1 + kMT * kLd2;
+constexpr int kOffU = kOffW3 + 256 * kLd3;   // x tile, later h2 tile (one per tile in flight)
+constexpr int kOffH1 = kOffU + 2 * kMT * kLd3;
+constexpr int kMlpLdsElems = kOffH1 + 2 * kMT * kLd2;
+constexpr int kMlpThreads = 512;              // two tiles at a time, four wavefronts each
 constexpr size_t kMlpLdsBytes = 2 * (size_t)kMlpLdsElems;
 
 __device__ __forceinline__ bf16x8_t lds_frag(const uint16_t* base, int row, int ld, int k)
@@ -222,38 +223,50 @@ __device__ __forceinline__ bf16x8_t lds_frag(const uint16_t* base, int row, int 
     return __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u16x8_t*>(base + row * ld + k));
 }
 
-__global__ __launch_bounds__(256) void mlp_pool_kernel(MlpArgs g)
+__global__ __launch_bounds__(kMlpThreads) void mlp_pool_kernel(MlpArgs g)
 {
     extern __shared__ __attribute__((aligned(16))) uint16_t sm16[];
     uint16_t* W1s = sm16 + kOffW1;
     uint16_t* W2s = sm16 + kOffW2;
     uint16_t* W3s = sm16 + kOffW3;
-    uint16_t* U = sm16 + kOffU;
-    uint16_t* H1s = sm16 + kOffH1;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int half = threadIdx.x >> 8;           // which of the two tiles in flight
+    const int tid = threadIdx.x & 255, lane = tid & 63, wave = tid >> 6;
+    uint16_t* U = sm16 + kOffU + half * kMT * kLd3;
+    uint16_t* H1s = sm16 + kOffH1 + half * kMT * kLd2;
     const int fr = lane & 15, fk = 8 * (lane >> 4);
     // weights, transposed to [column][k] BF16
-    for (int e = tid; e < 64 * 32; e += 256) {
+    for (int e = threadIdx.x; e < 64 * 32; e += kMlpThreads) {
         const int n = e % 64, k = e / 64;
         W1s[n * kLd1 + k] = to_bf16(k < 3 ? g.W1[k * 64 + n] : 0.f);
     }
-    for (int e = tid; e < 128 * 64; e += 256) {
+    for (int e = threadIdx.x; e < 128 * 64; e += kMlpThreads) {
         const int n = e % 128, k = e / 128;
         W2s[n * kLd2 + k] = to_bf16(g.W2[k * 128 + n]);
     }
-    for (int e = tid; e < 256 * 128; e += 256) {
+    for (int e = threadIdx.x; e < 256 * 128; e += kMlpThreads) {
         const int n = e % 256, k = e / 256;
         W3s[n * kLd3 + k] = to_bf16(g.W3[k * 256 + n]);
     }
     const int64_t ntiles = g.rows / kMT;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // each half takes every other tile of the workgroup's share; the loop
+    // count is the same for all threads (the barriers are workgroup-wide)
+    // and a half without a tile skips the work. The tile's 64 x 3 inputs,
+    // one value per thread below 192, are loaded a round ahead.
+    int64_t base = 2 * (int64_t)blockIdx.x;
+    float xv = (base + half < ntiles && tid < 3 * kMT) ? g.X[(base + half) * kMT * 3 + tid] : 0.f;
+    for (; base < ntiles; base += 2 * (int64_t)gridDim.x) {
+        const int64_t tile = base + half;
+        const bool live = tile < ntiles;
         const int64_t m0 = tile * kMT;
         const int64_t cloud = m0 / g.P;
         const int64_t rbase = m0 - cloud * g.P;
         for (int e = tid; e < kMT * 32; e += 256) {
             const int r = e / 32, k = e % 32;
-            U[r * kLd1 + k] = to_bf16(k < 3 ? g.X[(m0 + r) * 3 + k] : 0.f);
+            if (k >= 3) U[r * kLd1 + k] = 0;
         }
+        if (tid < 3 * kMT) U[(tid / 3) * kLd1 + tid % 3] = to_bf16(xv);
+        const int64_t next = tile + 2 * (int64_t)gridDim.x;
+        if (next < ntiles && tid < 3 * kMT) xv = g.X[next * kMT * 3 + tid];
         __syncthreads();   // also orders the weight staging before the first tile
         // layer 1: wavefront w owns column block w, all four row blocks
         {
@@ -347,7 +360,7 @@ __global__ __launch_bounds__(256) void mlp_pool_kernel(MlpArgs g)
                 best = o > best ? o : best;
                 o = __shfl_xor(best, 32);
                 best = o > best ? o : best;
-                if (lane < 16) atomicMax(g.keys + cloud * 256 + col, best);
+                if (live && lane < 16) atomicMax(g.keys + cloud * 256 + col, best);
             }
         }
         __syncthreads();   // the next tile overwrites U and H1s

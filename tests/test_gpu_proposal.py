@@ -316,3 +316,20 @@ def test_fused_per_point_kernel_matches_the_gemm_chain(P, B):
     assert np.abs(got - want).max() <= 1e-5 * np.abs(want).max()
     assert rows == 2 * B * P
     m.close()
+
+
+@pytest.mark.parametrize("M,N,K", [(256, 64, 3), (192, 128, 64), (128, 256, 128)])
+def test_matrix_core_product_is_bitwise_symmetric_in_its_operands(M, N, K):
+    """(x W)^T and W^T x^T from the BF16 matrix-core product have the same
+    bits: the fused per-point kernel takes the transposed form and the
+    backward recomputes the untransposed one at the winning points."""
+    rng = np.random.default_rng(M + N + K)
+    X = rng.standard_normal((M, K)).astype(np.float32)
+    W = rng.standard_normal((K, N)).astype(np.float32)
+    Xd, Wd = _cuda(X), _cuda(W)
+    C = torch.empty(M, N, dtype=torch.float32, device="cuda")
+    Ct = torch.empty(N, M, dtype=torch.float32, device="cuda")
+    PR.stein_icp_gemm_bf16(Xd, Wd, C)
+    PR.stein_icp_gemm_bf16(Wd, Xd, Ct, ta=1, tb=1)
+    torch.cuda.synchronize()
+    assert torch.equal(C, Ct.t())
