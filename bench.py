@@ -87,7 +87,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="kinect", choices=["cuboid", "kinect", "lidar", "batched", "proposal"])
-    ap.add_argument("--pairs", type=int, default=64, help="pairs of the batched workload")
+    ap.add_argument("--pairs", type=int, default=64, help="pairs of the batched and proposal workloads")
+    ap.add_argument("--workers", type=int, default=16,
+                    help="host processes generating the proposal workload's pairs (1: in process)")
     ap.add_argument("--nn", default="fp32", choices=["fp32", "bf16"],
                     help="nearest-neighbour search: exact FP32, or BF16 matrix-core screen + FP32 rerank")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -333,7 +335,7 @@ def run_proposal(args):
     by 30 iterations, both batched per generator, scored by the set distance
     to an independent 300-iteration reference run."""
     import multiprocessing as mp
-    pool = mp.get_context("fork").Pool(16)      # before any GPU use
+    pool = mp.get_context("fork").Pool(args.workers) if args.workers > 1 else None   # before any GPU use
     import torch
     from paper_2106_03287_amd import proposal as PR
     from paper_2106_03287_amd import train_proposal as TP
@@ -341,7 +343,8 @@ def run_proposal(args):
     cfg = PR.stein_icp_proposal_default_config(num_particles=100, points=4096, max_batch=32)
     model = PR.Proposal(cfg, np.load(weights, allow_pickle=False))
     ds, X, _ = TP.build_dataset(model, "test", args.pairs, pool, label=False)
-    pool.close()
+    if pool is not None:
+        pool.close()
     res = TP.evaluate(model, ds, X)
     n = sum(r["pairs"] for r in res.values())
     prop_ms = sum(r["network_ms"] + r["proposal_iter_ms_30"] for r in res.values())
