@@ -48,9 +48,13 @@ extern "C" {
 
 /* Nearest-neighbour search (Eq. 1). FP32: exact squared distances in FP32
  * (dx, dy, dz in FP32, d = fma(dz,dz, fma(dy,dy, dx*dx))), lowest index on
- * ties. BF16_RERANK: candidates screened by |a|^2 + |b|^2 - 2 a.b on BF16
- * matrix cores with FP32 accumulation, the best 8 re-ranked with the FP32
- * distance above. */
+ * ties. BF16_RERANK: the same answer, found faster: candidates screened by
+ * |a|^2 + |b|^2 - 2 a.b on BF16 matrix cores with FP32 accumulation (centred
+ * coordinates split into three BF16 parts), the best re-ranked with the FP32
+ * distance above, and every answer certified against a bound on the screen's
+ * error; a query whose certificate fails is searched again in FP32. Far from
+ * the centroid the bound widens and more queries take the FP32 path (LiDAR
+ * scale: most of them). */
 enum { STEIN_ICP_NN_FP32 = 0, STEIN_ICP_NN_BF16_RERANK = 1 };
 /* Update rule: Adam on -phi (Sec. V), or theta += lr * phi (Eq. 12). */
 enum { STEIN_ICP_OPT_ADAM = 0, STEIN_ICP_OPT_SGD = 1 };

@@ -19,9 +19,21 @@
 // sequence as the FP32 search) of its four references in its best block; the
 // four lanes of a query merge their (distance, tile) keys. The key format is
 // the FP32 search's, so chunk reduction and tile resolution downstream are
-// shared. The screen can miss the true neighbour when BF16 rounding reorders
-// near-equal candidates; the result is then another reference with its exact
-// distance (the miss rate is measured by the tests).
+// shared.
+//
+// Certificate: the result is the FP32 search's exact chunk minimum, ties
+// included. Let S be the screened and F the FP32 distance of a reference.
+// |S - F| <= eps = 28 u (|q_c| + R)^2 + 6.2 u F (u = 2^-24, R the pair's
+// largest centred reference norm): 23 FP32 additions of 24 exact BF16
+// products whose magnitudes sum to at most (|q_c| + |r_c|)^2, the dropped
+// BF16 cross terms and the FP32 norms, the FP32 centring, and the FP32
+// direct difference. Each lane also keeps s2, the smallest block minimum of
+// its rows outside its best block. After the workgroup merges its keys into
+// the chunk minimum F_wg, a lane whose references outside its best block all
+// satisfy F > F_wg -- guaranteed when s2 - 32 u (|q_c| + R)^2 > F_wg (1 + 8 u)
+// -- has lost nothing; otherwise that lane's own rows of its wavefront's
+// blocks are searched again in FP32 by the wavefront and folded into the
+// chunk minimum. The result is the FP32 search's key, ties included.
 #pragma once
 
 #include "common.hpp"
@@ -152,11 +164,12 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     const int64_t t1 = (ntiles * (wave + 1)) / W;
     const uint4* __restrict__ ap = a.apack + pd.apack_off + (c0 / kTile) * kWave + lane;
 
-    float best[G];
+    float best[G], sec[G];   // best block minimum, and the smallest of the other blocks
     int32_t bblk[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         best[g] = __builtin_inff();
+        sec[g] = __builtin_inff();
         bblk[g] = (int32_t)t0;
     }
     uint4 anext = t0 < t1 ? ap[t0 * kWave] : make_uint4(0u, 0u, 0u, 0u);
@@ -174,6 +187,7 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const float mn = __builtin_fminf(__builtin_fminf(acc[g][0], acc[g][1]), __builtin_fminf(acc[g][2], acc[g][3]));
+            sec[g] = __builtin_fminf(sec[g], __builtin_fmaxf(best[g], mn));
             const bool better = mn < best[g];
             best[g] = better ? mn : best[g];
             bblk[g] = better ? (int32_t)tt : bblk[g];
@@ -202,18 +216,65 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     }
 
     // lanes 0..15 hold the merged keys of the G groups; merge the W waves
+    // into the chunk minimum of each query (kept in sk[0])
 #pragma unroll
     for (int g = 0; g < G; ++g)
         if (s == 0) sk[wave][16 * g + j] = key[g];
     __syncthreads();
     for (int jj = threadIdx.x; jj < kWave * Q; jj += kWave * W) {
-        const int64_t qi = qbase + jj;
-        if (qi < nq) {
-            uint64_t k0 = sk[0][jj];
+        uint64_t k0 = sk[0][jj];
 #pragma unroll
-            for (int v = 1; v < W; ++v) k0 = min(k0, sk[v][jj]);
-            a.partial[pd.part_off + (int64_t)w.chunk * nq + qi] = k0;
+        for (int v = 1; v < W; ++v) k0 = min(k0, sk[v][jj]);
+        sk[0][jj] = k0;
+    }
+    __syncthreads();
+    // certificate of every lane against the chunk minimum; a lane that fails
+    // has its own rows of its own blocks (4 (t1 - t0) references) searched
+    // again in FP32 by its wavefront, folded into the chunk minimum in LDS
+    if (t0 < t1) {
+        constexpr double u = 0x1.0p-24;
+        const int64_t nref = 4 * (t1 - t0);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int64_t qi = qbase + 16 * g + j;
+            bool fail = false;
+            if (qi < nq) {
+                const float fwg = __uint_as_float((uint32_t)(sk[0][16 * g + j] >> 32));
+                const float4 qf = a.queries[pd.q_off + qi];
+                float c[3];
+                {
+#pragma clang fp contract(off)
+                    c[0] = qf.x - pd.c0[0];
+                    c[1] = qf.y - pd.c0[1];
+                    c[2] = qf.z - pd.c0[2];
+                }
+                const double qn = sqrt((double)c[0] * c[0] + (double)c[1] * c[1] + (double)c[2] * c[2]);
+                const double span = (qn + (double)pd.c0[3]) * (1.0 + 0x1.0p-20);
+                const double margin = 32.0 * u * span * span;
+                fail = !((double)sec[g] - margin > (double)fwg * (1.0 + 8.0 * u));
+            }
+            unsigned long long mask = __ballot(fail);
+            while (mask != 0ull) {   // wave-uniform
+                const int b = __ffsll((long long)mask) - 1;
+                mask &= mask - 1ull;
+                const int fj = b & 15, fs = b >> 4;
+                const float4 qf = a.queries[pd.q_off + qbase + 16 * g + fj];
+                uint64_t kb = ~0ull;
+                for (int64_t e = lane; e < nref; e += kWave) {
+                    const int64_t r = c0 + (t0 + e / 4) * kTile + 4 * fs + (e & 3);
+                    const float4 rr = a.ref4[pd.ref_off + r];
+                    kb = min(kb, pack_key(dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z), (uint32_t)(r / kTile)));
+                }
+#pragma unroll
+                for (int o = kWave / 2; o > 0; o >>= 1) kb = min(kb, (uint64_t)__shfl_xor((unsigned long long)kb, o));
+                if (lane == 0) atomicMin((unsigned long long*)&sk[0][16 * g + fj], (unsigned long long)kb);
+            }
         }
+    }
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < kWave * Q; jj += kWave * W) {
+        const int64_t qi = qbase + jj;
+        if (qi < nq) a.partial[pd.part_off + (int64_t)w.chunk * nq + qi] = sk[0][jj];
     }
     __syncthreads();
 }

@@ -40,6 +40,28 @@ int fail(int code, const std::string& msg)
     } while (0)
 
 inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Centre of the BF16 screen (the reference centroid, rounded to FP32) in
+// c0[0..2] and, in c0[3], an upper bound of the norms of the centred
+// references as the kernels form them (FP32 differences), which sizes the
+// screen's error bound.
+void bf16_centre(const float* xyz, int64_t n, PairDesc& pd)
+{
+    double acc[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) acc[d] += xyz[3 * i + d];
+    for (int d = 0; d < 3; ++d) pd.c0[d] = std::isfinite(acc[d]) ? (float)(acc[d] / n) : 0.0f;
+    double r2 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double q = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const float c = xyz[3 * i + d] - pd.c0[d];   // FP32, as in the kernels
+            q += (double)c * c;
+        }
+        r2 = std::max(r2, q);
+    }
+    pd.c0[3] = std::nextafter((float)(std::sqrt(r2) * (1.0 + 0x1.0p-20)), INFINITY);
+}
 inline int64_t ceil_div(int64_t v, int64_t a) { return (v + a - 1) / a; }
 inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -676,10 +698,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
                 delete c;
                 return fail(STEIN_ICP_E_DEVICE, "reading the reference cloud for its centroid failed");
             }
-            double acc[3] = {0, 0, 0};
-            for (int64_t i = 0; i < pd.n_ref; ++i)
-                for (int d = 0; d < 3; ++d) acc[d] += h[3 * i + d];
-            for (int d = 0; d < 3; ++d) pd.c0[d] = std::isfinite(acc[d]) ? (float)(acc[d] / pd.n_ref) : 0.0f;
+            bf16_centre(h.data(), pd.n_ref, pd);
             pd.apack_off = apack_n;
             apack_n += pd.n_ref_pad / kTile * kWave;
         }
@@ -1046,10 +1065,7 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
         std::vector<float> h((size_t)n_ref * 3);
         if (hipMemcpy(h.data(), ref_xyz, 12 * (size_t)n_ref, hipMemcpyDeviceToHost) != hipSuccess)
             return fail(STEIN_ICP_E_DEVICE, "reading the reference cloud for its centroid failed");
-        double acc[3] = {0, 0, 0};
-        for (int64_t i = 0; i < n_ref; ++i)
-            for (int d = 0; d < 3; ++d) acc[d] += h[3 * i + d];
-        for (int d = 0; d < 3; ++d) pd.c0[d] = std::isfinite(acc[d]) ? (float)(acc[d] / n_ref) : 0.0f;
+        bf16_centre(h.data(), n_ref, pd);
         pd.apack_off = 0;
     }
     std::vector<PairDesc> v{pd};
