@@ -26,26 +26,27 @@ VALU_PEAK_TFLOPS = 157.3    # MI355X FP32 vector peak: 256 CUs x 2.4 GHz x 256 F
 MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
 FLOPS_PER_PAIR = 9          # 3 sub + 3 mul + 2 add (squared distance) + 1 compare
 NN_SOURCES = ["paper_2106_03287_amd/csrc/nn.hpp", "paper_2106_03287_amd/csrc/common.hpp"]
+NN_BF16_SOURCES = NN_SOURCES + ["paper_2106_03287_amd/csrc/nn_bf16.hpp"]
 
 
-def nn_source_sha():
+def nn_source_sha(nn="fp32"):
     import hashlib
     h = hashlib.sha256()
-    for f in NN_SOURCES:
+    for f in (NN_BF16_SOURCES if nn == "bf16" else NN_SOURCES):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, tiling):
+def measured_traffic(workload, tiling, nn="fp32"):
     """HBM bytes per NN launch from the committed counter runs, if they were
-    taken on the current kernel source, this workload and this NN shape;
-    else None."""
-    path = os.path.join(ROOT, "profiles", "nn_fp32_traffic.json")
+    taken on the current kernel source, this workload, search mode and NN
+    shape; else None."""
+    path = os.path.join(ROOT, "profiles", "nn_traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path)).get(workload)
+    rec = json.load(open(path)).get(workload if nn == "fp32" else f"{workload}:{nn}")
     shape = "%d,%d,%d,%d" % (tiling["queries_per_lane"], tiling["waves"], tiling["chunk"], tiling["persist"])
-    if not rec or rec.get("source_sha") != nn_source_sha() or rec.get("tiling") != shape:
+    if not rec or rec.get("source_sha") != nn_source_sha(nn) or rec.get("tiling") != shape:
         return None
     return rec["hbm_bytes_per_launch"]
 
@@ -73,6 +74,12 @@ def cpu_baseline(prob, budget_s=15.0):
 # NN shapes (queries per lane, wavefronts per workgroup, chunk, persistent
 # workgroups per CU) pinned from a sweep of the tuner's space on one MI355X
 # (full solves, median of 3); the runner-up shapes are within 2 %
+# search mode of --nn auto: the certified BF16 screen returns the FP32 search's
+# answers bit for bit; measured faster than the FP32 search on the Kinect
+# (1.25x on the NN stage) and LiDAR (1.37x) workloads, slower on the small
+# cuboid clouds, where the search is latency-bound
+AUTO_NN = {"cuboid": "fp32", "kinect": "bf16", "lidar": "bf16"}
+
 PINNED_TILING = {
     ("kinect", "fp32"): "4,16,2048,2",
     ("kinect", "bf16"): "2,8,20096,0",
@@ -90,8 +97,9 @@ def main():
     ap.add_argument("--pairs", type=int, default=64, help="pairs of the batched and proposal workloads")
     ap.add_argument("--workers", type=int, default=16,
                     help="host processes generating the proposal workload's pairs (1: in process)")
-    ap.add_argument("--nn", default="fp32", choices=["fp32", "bf16"],
-                    help="nearest-neighbour search: exact FP32, or BF16 matrix-core screen + FP32 rerank")
+    ap.add_argument("--nn", default="auto", choices=["auto", "fp32", "bf16"],
+                    help="nearest-neighbour search: FP32, or the certified BF16 matrix-core screen (the same "
+                         "answers); auto takes the faster for the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", type=int, default=0,
                     help="tune the NN shape at init instead of using the pinned shape of the workload")
@@ -111,6 +119,8 @@ def main():
     import synth
     from paper_2106_03287_amd import stein_icp as S
 
+    if args.nn == "auto":
+        args.nn = AUTO_NN.get(args.workload, "fp32")
     if not args.tiling and not args.autotune:
         args.tiling = PINNED_TILING.get((args.workload, args.nn), "")
         if not args.tiling:
@@ -176,7 +186,8 @@ def main():
         # 16 queries x 16 references, i.e. 64 flops per pair
         mfma = pairs_per_launch * 64 / (nn_ms * 1e-3) / 1e12
         roofline = {"bound": "mfma", "achieved": round(mfma, 3), "peak": MFMA_BF16_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(mfma / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
+                    "unit": "TFLOP/s", "frac": round(mfma / MFMA_BF16_PEAK_TFLOPS, 4),
+                    "traffic": measured_traffic(prob.name, tiling, "bf16"),
                     "kernel": "nn_bf16_kernel", "avg_launch_ms": round(nn_ms, 5),
                     "pair_evals_per_launch": pairs_per_launch,
                     "alu_view": {"achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
@@ -187,9 +198,10 @@ def main():
                     "traffic": measured_traffic(prob.name, tiling),
                     "kernel": "nn_fp32_kernel", "avg_launch_ms": round(nn_ms, 5),
                     "pair_evals_per_launch": pairs_per_launch}
-    mismatch = None
+    mismatch, identical = None, None
     if args.nn == "bf16":
-        # matches of the first iteration against the exact FP32 search from the same state
+        # against the FP32 search from the same state: the first iteration's
+        # matches, and the particles after the whole solve (bit for bit)
         S.stein_icp_set_state(sol.ctx, theta0, zeros, zeros, 0)
         sol.step(1)
         mb = sol.diagnostics()["match"]
@@ -198,6 +210,10 @@ def main():
         ref32 = S.SteinICP(cfg32, src, ref, theta0, sched)
         ref32.step(1)
         mismatch = float((mb != ref32.diagnostics()["match"]).double().mean().item())
+        solve()
+        S.stein_icp_set_state(ref32.ctx, theta0, zeros, zeros, 0)
+        ref32.step(prob.T)
+        identical = bool(torch.equal(sol.particles(), ref32.particles()))
         ref32.close()
     sol.close()
 
@@ -223,7 +239,8 @@ def main():
         "init_ms": round(init_ms, 2),
         "nn_tiling": tiling,
         "nn_mismatch_vs_fp32": mismatch,
-        "nn_source_sha": nn_source_sha(),
+        "particles_identical_to_fp32_solve": identical,
+        "nn_source_sha": nn_source_sha(args.nn),
         "torch": torch.__version__,
         "roofline": roofline,
     }
