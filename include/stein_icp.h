@@ -53,8 +53,7 @@ extern "C" {
  * coordinates split into three BF16 parts), the best re-ranked with the FP32
  * distance above, and every answer certified against a bound on the screen's
  * error; a query whose certificate fails is searched again in FP32. Far from
- * the centroid the bound widens and more queries take the FP32 path (LiDAR
- * scale: most of them). */
+ * the centroid the bound widens and more queries take the FP32 path. */
 enum { STEIN_ICP_NN_FP32 = 0, STEIN_ICP_NN_BF16_RERANK = 1 };
 /* Update rule: Adam on -phi (Sec. V), or theta += lr * phi (Eq. 12). */
 enum { STEIN_ICP_OPT_ADAM = 0, STEIN_ICP_OPT_SGD = 1 };

@@ -38,11 +38,13 @@ class Config(C.Structure):
         ("prior", C.c_int32), ("pad_", C.c_int32),
         ("prior_mu", C.c_double * 6), ("prior_var_trans", C.c_double * 3),
         ("prior_kappa_rot", C.c_double * 3),
+        ("metric", C.c_int32), ("pad2_", C.c_int32),
     ]
 
 
 ADAM, SGD = 0, 1
 BW_MEDIAN, BW_FIXED = 0, 1
+POINT, PLANE = 0, 1
 
 _lib = None
 
@@ -69,8 +71,13 @@ def lib():
         L.or_median.restype = C.c_double
         L.or_svgd_phi.argtypes = [cfg, dp, dp, dp, dp]
         L.or_update.argtypes = [cfg, C.c_int64, dp, dp, dp, dp]
-        L.or_step.argtypes = [cfg, fp, fp, ip, dp, dp, dp, lp, dp, dp, dp, ip]
-        L.or_run.argtypes = [cfg, fp, fp, ip, C.c_int32, C.c_int32, dp, dp, dp, lp]
+        L.or_knn_f32.argtypes = [fp, C.c_int64, fp, C.c_int64, C.c_int32, ip, fp]
+        L.or_normals.argtypes = [fp, C.c_int64, C.c_int32, dp, dp]
+        L.or_plane_cost.argtypes = [dp, fp, fp, dp, ip, C.c_int32, ip]
+        L.or_plane_cost.restype = C.c_double
+        L.or_plane_gradient.argtypes = [dp, fp, fp, dp, ip, C.c_int32, ip, dp]
+        L.or_step.argtypes = [cfg, fp, fp, dp, ip, dp, dp, dp, lp, dp, dp, dp, ip]
+        L.or_run.argtypes = [cfg, fp, fp, dp, ip, C.c_int32, C.c_int32, dp, dp, dp, lp]
         _lib = L
     return _lib
 
@@ -93,12 +100,13 @@ def _i32(a):
 
 def make_config(K, m, N, M, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8,
                 optimizer=ADAM, bandwidth=BW_MEDIAN, h_fixed=(1.0, 1.0),
-                prior=None) -> Config:
+                prior=None, metric=POINT) -> Config:
     c = Config()
     c.K, c.m, c.N, c.M = int(K), int(m), int(N), int(M)
     c.lr, c.beta1, c.beta2, c.eps = lr, beta1, beta2, eps
     c.optimizer, c.bandwidth = optimizer, bandwidth
     c.h_fixed_trans, c.h_fixed_rot = h_fixed
+    c.metric = metric
     if prior is not None:
         c.prior = 1
         for i, v in enumerate(prior["mu"]):
@@ -164,6 +172,55 @@ def icp_gradient(theta, src, ref, batch, match):
     return g
 
 
+def knn_f32(q, ref, k):
+    """k nearest references per query, ascending (distance, index); -1 / inf
+    beyond the reference count."""
+    q, ref = _f32(q).reshape(-1, 3), _f32(ref).reshape(-1, 3)
+    idx = np.empty((len(q), k), dtype=np.int32)
+    d2 = np.empty((len(q), k), dtype=np.float32)
+    lib().or_knn_f32(_p(q, C.c_float), len(q), _p(ref, C.c_float), len(ref), int(k),
+                     _p(idx, C.c_int32), _p(d2, C.c_float))
+    return idx, d2
+
+
+def normals(ref, k):
+    """Unit normals (M x 3, zero where undefined) and the neighbourhood
+    covariance eigenvalues (M x 3, ascending)."""
+    ref = _f32(ref).reshape(-1, 3)
+    n = np.empty((len(ref), 3))
+    w = np.empty((len(ref), 3))
+    lib().or_normals(_p(ref, C.c_float), len(ref), int(k), _p(n, C.c_double), _p(w, C.c_double))
+    return n, w
+
+
+def plane_cost(theta, src, ref, nrm, batch, match):
+    th, src, ref, nrm = _f64(theta), _f32(src), _f32(ref), _f64(nrm)
+    batch, match = _i32(batch), _i32(match)
+    return lib().or_plane_cost(_p(th, C.c_double), _p(src, C.c_float), _p(ref, C.c_float),
+                               _p(nrm, C.c_double), _p(batch, C.c_int32), len(batch), _p(match, C.c_int32))
+
+
+def plane_gradient(theta, src, ref, nrm, batch, match):
+    th, src, ref, nrm = _f64(theta), _f32(src), _f32(ref), _f64(nrm)
+    batch, match = _i32(batch), _i32(match)
+    g = np.zeros(6)
+    lib().or_plane_gradient(_p(th, C.c_double), _p(src, C.c_float), _p(ref, C.c_float),
+                            _p(nrm, C.c_double), _p(batch, C.c_int32), len(batch), _p(match, C.c_int32),
+                            _p(g, C.c_double))
+    return g
+
+
+def _normals_arg(cfg, nrm, M):
+    if cfg.metric != PLANE:
+        return None, None
+    if nrm is None:
+        raise ValueError("the point-to-plane metric needs the reference normals")
+    nrm = _f64(nrm).reshape(-1, 3)
+    if len(nrm) != M:
+        raise ValueError("one normal per reference point")
+    return nrm, _p(nrm, C.c_double)
+
+
 def prior_grad(cfg: Config, theta):
     th = _f64(theta)
     out = np.zeros(6)
@@ -206,15 +263,17 @@ class State:
         return State(self.theta, self.mom, self.vel, int(self.t[0]))
 
 
-def step(cfg: Config, src, ref, batch, state: State):
-    """One iteration in place; returns diagnostics dict (gbar, phi, h, match)."""
+def step(cfg: Config, src, ref, batch, state: State, normals=None):
+    """One iteration in place; returns diagnostics dict (gbar, phi, h, match).
+    normals: M x 3, for the point-to-plane metric."""
     src, ref, batch = _f32(src), _f32(ref), _i32(batch)
+    keep, nptr = _normals_arg(cfg, normals, len(ref) // 3 if ref.ndim == 1 else len(ref))
     K, m = cfg.K, cfg.m
     gbar = np.zeros((K, 6))
     phi = np.zeros((K, 6))
     h = np.zeros(2)
     match = np.zeros((K, m), dtype=np.int32)
-    lib().or_step(C.byref(cfg), _p(src, C.c_float), _p(ref, C.c_float), _p(batch, C.c_int32),
+    lib().or_step(C.byref(cfg), _p(src, C.c_float), _p(ref, C.c_float), nptr, _p(batch, C.c_int32),
                   _p(state.theta, C.c_double), _p(state.mom, C.c_double),
                   _p(state.vel, C.c_double), _p(state.t, C.c_int64),
                   _p(gbar, C.c_double), _p(phi, C.c_double), _p(h, C.c_double),
@@ -222,10 +281,12 @@ def step(cfg: Config, src, ref, batch, state: State):
     return {"gbar": gbar, "phi": phi, "h": h, "match": match}
 
 
-def run(cfg: Config, src, ref, schedule, T, state: State):
-    """T iterations in place (iteration with step count t uses row t mod rows)."""
+def run(cfg: Config, src, ref, schedule, T, state: State, normals=None):
+    """T iterations in place (iteration with step count t uses row t mod rows).
+    normals: M x 3, for the point-to-plane metric."""
     src, ref, schedule = _f32(src), _f32(ref), _i32(schedule)
-    lib().or_run(C.byref(cfg), _p(src, C.c_float), _p(ref, C.c_float),
+    keep, nptr = _normals_arg(cfg, normals, len(ref) // 3 if ref.ndim == 1 else len(ref))
+    lib().or_run(C.byref(cfg), _p(src, C.c_float), _p(ref, C.c_float), nptr,
                  _p(schedule, C.c_int32), schedule.shape[0], int(T),
                  _p(state.theta, C.c_double), _p(state.mom, C.c_double),
                  _p(state.vel, C.c_double), _p(state.t, C.c_int64))

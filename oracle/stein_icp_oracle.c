@@ -41,6 +41,17 @@
  *  - Prior (Eqs. 14-15): Gaussian translation prior with variance sigma
  *    (Eq. 14 divides by it), von Mises rotation prior with concentration
  *    kappa; uniform (zero gradient) by default, as in the experiments.
+ *  - Point-to-plane metric (used for the paper's quantitative results,
+ *    Sec. V, and cited to Chen and Medioni in Sec. II without a formula):
+ *    matches still by Eq. 1; the residual of a matched pair is its
+ *    projection rho = n^T e onto the unit normal n of the matched reference
+ *    point; the cost is E_m = (1/2m) sum rho^2 (the scale of the
+ *    point-to-point reading above). Normals: eigenvector of the smallest
+ *    eigenvalue of the covariance of the point's k nearest references (the
+ *    point itself included, neighbours decided in FP32 like Eq. 1); zero
+ *    where the neighbourhood is a line or a point (middle eigenvalue at most
+ *    1e-10 of the trace). The sign of a normal is left open: neither the
+ *    cost nor its gradient depends on it.
  */
 #include <math.h>
 #include <stdint.h>
@@ -61,6 +72,8 @@ typedef struct {
     double prior_mu[6];
     double prior_var_trans[3];
     double prior_kappa_rot[3];
+    int32_t metric;         /* 0: point-to-point (Eqs. 4-5); 1: point-to-plane */
+    int32_t pad2_;
 } or_config;
 
 /* ---------------------------------------------------------------------- */
@@ -199,6 +212,191 @@ void or_prior_grad(const or_config *c, const double th[6], double out[6])
         out[3 + d] = -c->prior_kappa_rot[d] * sin(th[3 + d] - c->prior_mu[3 + d]);
 }
 
+/* ---------------------------------------------------------------------- */
+/* Point-to-plane metric                                                   */
+/* ---------------------------------------------------------------------- */
+
+/* The k nearest references of each query under Eq. 1's metric, decided in
+ * FP32 like the argmin: the k smallest (distance, index) pairs in ascending
+ * order, ties to the lower index. Slots beyond M hold index -1 and an
+ * infinite distance. Plain insertion into a sorted list of k. */
+void or_knn_f32(const float *q, int64_t nq, const float *ref, int64_t M, int32_t k,
+                int32_t *idx, float *d2)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nq; ++i) {
+        int32_t *bi = idx + i * k;
+        float *bd = d2 + i * k;
+        for (int32_t s = 0; s < k; ++s) {
+            bi[s] = -1;
+            bd[s] = INFINITY;
+        }
+        for (int64_t j = 0; j < M; ++j) {
+            const float d = or_dist2_f32(q + 3 * i, ref + 3 * j);
+            if (!(d < bd[k - 1])) continue;   /* equal distance: the lower index stays */
+            int32_t s = k - 1;
+            while (s > 0 && d < bd[s - 1]) {
+                bd[s] = bd[s - 1];
+                bi[s] = bi[s - 1];
+                --s;
+            }
+            bd[s] = d;
+            bi[s] = (int32_t)j;
+        }
+    }
+}
+
+/* Eigen-decomposition of a symmetric 3x3 matrix by cyclic Jacobi rotations:
+ * each rotation in the (p, q) plane zeroes A[p][q]; sweeps repeat until the
+ * off-diagonal part vanishes at FP64 precision. Eigenvalues w ascending,
+ * eigenvector i in column i of V (row-major). */
+static void jacobi_eigen3(const double A_in[9], double w[3], double V[9])
+{
+    double A[3][3], U[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            A[r][c] = A_in[3 * r + c];
+            U[r][c] = r == c ? 1.0 : 0.0;
+        }
+    static const int PQ[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+        if (off == 0.0 || off <= 1e-36 * dia) break;
+        for (int e = 0; e < 3; ++e) {
+            const int p = PQ[e][0], qq = PQ[e][1];
+            const double apq = A[p][qq];
+            if (apq == 0.0) continue;
+            const double th = (A[qq][qq] - A[p][p]) / (2.0 * apq);
+            double t;
+            if (fabs(th) > 1e150)
+                t = 0.5 / th;
+            else
+                t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+            /* A <- J^T A J with J the rotation by (c, sn) in the (p, q) plane */
+            for (int r = 0; r < 3; ++r) {
+                const double arp = A[r][p], arq = A[r][qq];
+                A[r][p] = c * arp - sn * arq;
+                A[r][qq] = sn * arp + c * arq;
+            }
+            for (int r = 0; r < 3; ++r) {
+                const double apr = A[p][r], aqr = A[qq][r];
+                A[p][r] = c * apr - sn * aqr;
+                A[qq][r] = sn * apr + c * aqr;
+            }
+            A[p][qq] = A[qq][p] = 0.0;
+            for (int r = 0; r < 3; ++r) {
+                const double urp = U[r][p], urq = U[r][qq];
+                U[r][p] = c * urp - sn * urq;
+                U[r][qq] = sn * urp + c * urq;
+            }
+        }
+    }
+    int order[3] = {0, 1, 2};
+    for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b)
+            if (A[order[b]][order[b]] < A[order[a]][order[a]]) {
+                const int tmp = order[a];
+                order[a] = order[b];
+                order[b] = tmp;
+            }
+    for (int i = 0; i < 3; ++i) {
+        w[i] = A[order[i]][order[i]];
+        for (int r = 0; r < 3; ++r) V[3 * r + i] = U[r][order[i]];
+    }
+}
+
+/* Unit normal of every reference point from its k nearest references (the
+ * point itself included; all M when M < k): the covariance
+ * (1/k) sum (p - mean)(p - mean)^T in FP64 and its eigenvector of the
+ * smallest eigenvalue; zero when the middle eigenvalue is at most 1e-10 of
+ * the trace (the neighbourhood spans no plane). normals: M x 3; eig
+ * (optional): M x 3 eigenvalues, ascending. */
+void or_normals(const float *ref, int64_t M, int32_t k, double *normals, double *eig)
+{
+    const int32_t kk = (int64_t)k < M ? k : (int32_t)M;
+    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)M * kk);
+    float *d2 = (float *)malloc(sizeof(float) * (size_t)M * kk);
+    or_knn_f32(ref, M, ref, M, kk, idx, d2);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < M; ++i) {
+        const int32_t *nb = idx + i * kk;
+        double mu[3] = {0, 0, 0};
+        for (int32_t s = 0; s < kk; ++s)
+            for (int d = 0; d < 3; ++d) mu[d] += ref[3 * (int64_t)nb[s] + d];
+        for (int d = 0; d < 3; ++d) mu[d] /= kk;
+        double C[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int32_t s = 0; s < kk; ++s) {
+            double v[3];
+            for (int d = 0; d < 3; ++d) v[d] = ref[3 * (int64_t)nb[s] + d] - mu[d];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) C[3 * r + c] += v[r] * v[c];
+        }
+        for (int e = 0; e < 9; ++e) C[e] /= kk;
+        double w[3], V[9];
+        jacobi_eigen3(C, w, V);
+        double n[3] = {V[0], V[3], V[6]};
+        const double trace = (w[0] + w[1]) + w[2];
+        if (w[1] > 1e-10 * trace) {
+            const double len = sqrt((n[0] * n[0] + n[1] * n[1]) + n[2] * n[2]);
+            for (int d = 0; d < 3; ++d) n[d] /= len;
+        } else {
+            n[0] = n[1] = n[2] = 0.0;
+        }
+        for (int d = 0; d < 3; ++d) normals[3 * i + d] = n[d];
+        if (eig)
+            for (int d = 0; d < 3; ++d) eig[3 * i + d] = w[d];
+    }
+    free(idx);
+    free(d2);
+}
+
+/* Point-to-plane minibatch cost E_m = (1/2m) sum_i (n_j^T e_i)^2, with
+ * j = match(i) and e_i = R s_i + u - r_j. */
+double or_plane_cost(const double th[6], const float *src, const float *ref, const double *normals,
+                     const int32_t *batch, int32_t m, const int32_t *match)
+{
+    double R[9], q[3];
+    or_rotation(th, R, NULL);
+    double acc = 0.0;
+    for (int32_t i = 0; i < m; ++i) {
+        or_transform(R, th, src + 3 * (int64_t)batch[i], q);
+        const float *r = ref + 3 * (int64_t)match[i];
+        const double *n = normals + 3 * (int64_t)match[i];
+        const double rho = (n[0] * (q[0] - r[0]) + n[1] * (q[1] - r[1])) + n[2] * (q[2] - r[2]);
+        acc += rho * rho;
+    }
+    return acc / (2.0 * m);
+}
+
+/* Its gradient: translation part (1/m) sum rho_i n_j, rotation part
+ * (1/m) sum rho_i n_j^T (dR/dtheta_d) s_i (Eq. 5 with e projected on n). */
+void or_plane_gradient(const double th[6], const float *src, const float *ref, const double *normals,
+                       const int32_t *batch, int32_t m, const int32_t *match, double g[6])
+{
+    double R[9], dR[27], q[3];
+    or_rotation(th, R, dR);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int32_t i = 0; i < m; ++i) {
+        const float *s = src + 3 * (int64_t)batch[i];
+        or_transform(R, th, s, q);
+        const float *r = ref + 3 * (int64_t)match[i];
+        const double *n = normals + 3 * (int64_t)match[i];
+        const double e[3] = {q[0] - r[0], q[1] - r[1], q[2] - r[2]};
+        const double rho = (n[0] * e[0] + n[1] * e[1]) + n[2] * e[2];
+        for (int d = 0; d < 3; ++d) acc[d] += rho * n[d];
+        for (int d = 0; d < 3; ++d) {
+            const double *D = dR + 9 * d;
+            double v[3];
+            for (int row = 0; row < 3; ++row)
+                v[row] = (D[3 * row + 0] * s[0] + D[3 * row + 1] * s[1]) + D[3 * row + 2] * s[2];
+            acc[3 + d] += rho * ((n[0] * v[0] + n[1] * v[1]) + n[2] * v[2]);
+        }
+    }
+    for (int d = 0; d < 6; ++d) g[d] = acc[d] / m;
+}
+
 /* Wrapped angle difference used by the rotation kernel (Eq. 17). */
 static double wrap_angle(double x) { return atan2(sin(x), cos(x)); }
 
@@ -323,9 +521,10 @@ void or_update(const or_config *c, int64_t t, double *theta, double *mom, double
  * minibatch by every particle, match each transformed point (Eq. 1), mean
  * gradients per particle (Eqs. 4-5), Stein direction (Eq. 16), update.
  * *t counts completed updates and is advanced by one. Optional outputs (may
- * be NULL): gbar K x 6, phi K x 6, h[2], match K x m. */
-void or_step(const or_config *c, const float *src, const float *ref, const int32_t *batch,
-             double *theta, double *mom, double *vel, int64_t *t,
+ * be NULL): gbar K x 6, phi K x 6, h[2], match K x m. normals (M x 3) is
+ * read only with the point-to-plane metric. */
+void or_step(const or_config *c, const float *src, const float *ref, const double *normals,
+             const int32_t *batch, double *theta, double *mom, double *vel, int64_t *t,
              double *gbar_out, double *phi_out, double *h_out, int32_t *match_out)
 {
     const int K = c->K, m = c->m;
@@ -347,8 +546,12 @@ void or_step(const or_config *c, const float *src, const float *ref, const int32
     or_nn_f32(q32, nq, ref, c->M, match, NULL);
     for (int k = 0; k < K; ++k) {
         double pg[6];
-        or_icp_gradient(theta + 6 * (int64_t)k, src, ref, batch, m, match + (int64_t)k * m,
-                        gbar + 6 * (int64_t)k);
+        if (c->metric == 1)
+            or_plane_gradient(theta + 6 * (int64_t)k, src, ref, normals, batch, m, match + (int64_t)k * m,
+                              gbar + 6 * (int64_t)k);
+        else
+            or_icp_gradient(theta + 6 * (int64_t)k, src, ref, batch, m, match + (int64_t)k * m,
+                            gbar + 6 * (int64_t)k);
         or_prior_grad(c, theta + 6 * (int64_t)k, pg);
         for (int d = 0; d < 6; ++d)
             G[6 * (int64_t)k + d] = -(double)c->N * gbar[6 * (int64_t)k + d] + pg[d];
@@ -370,12 +573,12 @@ void or_step(const or_config *c, const float *src, const float *ref, const int32
 }
 
 /* T iterations; iteration with step count t uses schedule row t mod rows. */
-void or_run(const or_config *c, const float *src, const float *ref,
+void or_run(const or_config *c, const float *src, const float *ref, const double *normals,
             const int32_t *schedule, int32_t rows, int32_t T,
             double *theta, double *mom, double *vel, int64_t *t)
 {
     for (int32_t it = 0; it < T; ++it) {
         const int32_t *batch = schedule + (int64_t)(*t % rows) * c->m;
-        or_step(c, src, ref, batch, theta, mom, vel, t, NULL, NULL, NULL, NULL);
+        or_step(c, src, ref, normals, batch, theta, mom, vel, t, NULL, NULL, NULL, NULL);
     }
 }
