@@ -49,9 +49,10 @@
  *    point-to-point reading above). Normals: eigenvector of the smallest
  *    eigenvalue of the covariance of the point's k nearest references (the
  *    point itself included, neighbours decided in FP32 like Eq. 1); zero
- *    where the neighbourhood is a line or a point (middle eigenvalue at most
- *    1e-10 of the trace). The sign of a normal is left open: neither the
- *    cost nor its gradient depends on it.
+ *    where that eigenvalue is not separated from the middle one by more
+ *    than 1e-10 of the trace (a line, a point or an isotropic
+ *    neighbourhood: no unique plane). The sign of a normal is left open:
+ *    neither the cost nor its gradient depends on it.
  */
 #include <math.h>
 #include <stdint.h>
@@ -310,8 +311,8 @@ static void jacobi_eigen3(const double A_in[9], double w[3], double V[9])
 /* Unit normal of every reference point from its k nearest references (the
  * point itself included; all M when M < k): the covariance
  * (1/k) sum (p - mean)(p - mean)^T in FP64 and its eigenvector of the
- * smallest eigenvalue; zero when the middle eigenvalue is at most 1e-10 of
- * the trace (the neighbourhood spans no plane). normals: M x 3; eig
+ * smallest eigenvalue; zero when the smallest and middle eigenvalues are
+ * within 1e-10 of the trace of each other (no unique plane). normals: M x 3; eig
  * (optional): M x 3 eigenvalues, ascending. */
 void or_normals(const float *ref, int64_t M, int32_t k, double *normals, double *eig)
 {
@@ -338,7 +339,7 @@ void or_normals(const float *ref, int64_t M, int32_t k, double *normals, double 
         jacobi_eigen3(C, w, V);
         double n[3] = {V[0], V[3], V[6]};
         const double trace = (w[0] + w[1]) + w[2];
-        if (w[1] > 1e-10 * trace) {
+        if (w[1] - w[0] > 1e-10 * trace) {
             const double len = sqrt((n[0] * n[0] + n[1] * n[1]) + n[2] * n[2]);
             for (int d = 0; d < 3; ++d) n[d] /= len;
         } else {

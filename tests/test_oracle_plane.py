@@ -107,6 +107,10 @@ def test_normals_of_lines_and_repeated_points_are_zero(orc):
     same = np.tile(np.array([[0.5, -0.25, 2.0]], np.float32), (20, 1))
     n, w = orc.normals(same, 8)
     assert np.all(n == 0.0) and np.all(w == 0.0)
+    # a grid point with its six axis neighbours: isotropic, no unique plane
+    star = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.float32)
+    n, w = orc.normals(star, 7)
+    assert np.all(n[0] == 0.0) and w[0][0] == w[0][2]
     # a plane grid keeps its normals
     g = np.arange(6) / 8.0
     x, y = np.meshgrid(g, g)
