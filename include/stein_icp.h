@@ -65,6 +65,18 @@ enum { STEIN_ICP_BW_MEDIAN = 0, STEIN_ICP_BW_FIXED = 1 };
  * translation (Eq. 14, variance prior_var_trans) and von Mises rotation
  * (Eq. 15, concentration prior_kappa_rot) around prior_mu. */
 enum { STEIN_ICP_PRIOR_UNIFORM = 0, STEIN_ICP_PRIOR_GAUSS_VONMISES = 1 };
+/* ICP error metric of the gradient. POINT: Eqs. 4-5, e = R s + u - r.
+ * PLANE: point-to-plane (the metric of the paper's quantitative results,
+ * Sec. V; cited to Chen and Medioni in Sec. II): matches still by Eq. 1,
+ * e replaced by its projection rho n on the unit normal n of the matched
+ * reference (rho = n^T e), i.e. the gradient of (1/2m) sum rho^2. Normals
+ * are computed at init: the eigenvector of the smallest eigenvalue of the
+ * FP64 covariance of each reference point's normal_k nearest references
+ * (itself included, FP32 distances as in Eq. 1, ties to the lower index);
+ * zero where the smallest and middle eigenvalues lie within 1e-10 of the
+ * trace of each other (no unique plane). The sign of a normal is not
+ * defined; the gradient does not depend on it. */
+enum { STEIN_ICP_METRIC_POINT = 0, STEIN_ICP_METRIC_PLANE = 1 };
 
 typedef struct stein_icp_config {
     uint32_t struct_size;    /* sizeof(stein_icp_config): ABI version check */
@@ -90,6 +102,8 @@ typedef struct stein_icp_config {
     int64_t n_scale;         /* N multiplying the mean gradient (Eq. 16); 0 = source size */
     int32_t use_graph;       /* 1: stein_icp_step replays captured hipGraphs */
     int32_t autotune;        /* 1: time candidate NN tile shapes at init and keep the best */
+    int32_t metric;          /* STEIN_ICP_METRIC_* */
+    int32_t normal_k;        /* neighbours per normal (PLANE), 3 <= normal_k <= 32 */
 } stein_icp_config;
 
 typedef struct stein_icp_ctx stein_icp_ctx;
@@ -97,7 +111,7 @@ typedef struct stein_icp_ctx stein_icp_ctx;
 /* Fill `cfg` with the defaults: K 100, m 300, schedule_rows 1, lr 0.01,
  * beta1 0.9, beta2 0.999, eps 1e-8, seed 0, init +-0.2 m / +-pi/4 around 0,
  * FP32 search, Adam, median bandwidth, uniform prior, n_scale 0, graphs on,
- * autotune off. */
+ * autotune off, point-to-point metric, normal_k 10. */
 void stein_icp_default_config(stein_icp_config *cfg);
 
 /* Create a context for one cloud pair. Blocking: packs the clouds into the
@@ -204,6 +218,30 @@ const char *stein_icp_last_error(void);
  * Allocates and frees its own scratch; blocking. */
 int stein_icp_nn(const float *q_xyz, int64_t nq, const float *ref_xyz, int64_t n_ref,
                  int32_t mode, int32_t *idx, float *d2, void *hip_stream);
+
+/* Standalone k-nearest-neighbour search under Eq. 1's metric: for each
+ * query the k smallest (FP32 squared distance, index) pairs in ascending
+ * order, ties to the lower index (the neighbourhoods of the normals).
+ *   q_xyz: device FP32 nq x 3; ref_xyz: device FP32 n_ref x 3; 1 <= k <= 32;
+ *   idx: device int32 nq x k (-1 past n_ref); d2: device FP32 nq x k
+ *   (+inf past n_ref).
+ * Allocates and frees its own scratch; blocking. */
+int stein_icp_knn(const float *q_xyz, int64_t nq, const float *ref_xyz, int64_t n_ref,
+                  int32_t k, int32_t *idx, float *d2, void *hip_stream);
+
+/* Normals of a cloud, as the point-to-plane metric computes them at init
+ * (see STEIN_ICP_METRIC_PLANE), from each point's k nearest points.
+ *   ref_xyz: device FP32 n_ref x 3; 3 <= k <= 32 (all points when
+ *   n_ref < k); normals: device FP64 n_ref x 3 (unit or zero); eig: device
+ *   FP64 n_ref x 3, the covariance eigenvalues in ascending order, or NULL.
+ * Allocates and frees its own scratch; blocking. */
+int stein_icp_normals(const float *ref_xyz, int64_t n_ref, int32_t k, double *normals,
+                      double *eig, void *hip_stream);
+
+/* The normals a point-to-plane context computed at init: device FP64
+ * (sum of n_ref over its pairs) x 3, pairs in order. E_STATE for a
+ * point-to-point context. Stream-ordered. */
+int stein_icp_get_normals(const stein_icp_ctx *ctx, double *out, void *hip_stream);
 
 /* Host helpers (no device needed). The library's own generator is
  * SplitMix64 (Steele, Lea, Flood 2014): uniform doubles from the top 53 bits,

@@ -1,5 +1,5 @@
-// Per-particle mean point-to-point gradient (Eqs. 4-5), fused with the final
-// reduction of the per-chunk nearest-neighbour keys.
+// Per-particle mean gradient (Eqs. 4-5, point-to-point or point-to-plane),
+// fused with the final reduction of the per-chunk nearest-neighbour keys.
 //
 // One group of 512 threads per particle, two groups to a workgroup. Each
 // thread takes minibatch points i = t, t + 512, ...: it reduces the chunk
@@ -7,7 +7,9 @@
 // winning tile to the matched reference index, recomputes the FP64
 // transform s' = R s + u, forms the
 // residual e = s' - r and the six contributions e and e^T (dR/dtheta_d) s,
-// accumulating in FP64. The group's 512 partial sums are combined by a
+// accumulating in FP64. With the point-to-plane metric e is first replaced by
+// its projection rho n on the matched reference's unit normal n
+// (rho = n^T e), which gives rho n and rho n^T (dR/dtheta_d) s. The group's 512 partial sums are combined by a
 // fixed-shape tree in LDS, so the result does not depend on scheduling.
 #pragma once
 
@@ -27,6 +29,7 @@ struct GradArgs {
     const uint64_t* partial;
     int32_t* match;       // K*m per pair, pair-relative reference indices
     double* gbar;         // 6 per particle
+    const double* nrm;    // point-to-plane: 4 doubles (n, 0) per packed reference; NULL: point-to-point
     int32_t K, m, rows, pad_;
 };
 
@@ -60,7 +63,16 @@ __device__ __forceinline__ void grad_group(const GradArgs& a, int64_t pk, int64_
             transform_f64(P->R, P->u, s.x, s.y, s.z, q);
             {
 #pragma clang fp contract(off)
-                const double e0 = q[0] - (double)r.x, e1 = q[1] - (double)r.y, e2 = q[2] - (double)r.z;
+                double e0 = q[0] - (double)r.x, e1 = q[1] - (double)r.y, e2 = q[2] - (double)r.z;
+                if (a.nrm) {
+                    asm volatile("" ::: "memory");   // load the normal here, not earlier
+                    const double* n = a.nrm + 4 * (pd.ref_off + j);
+                    const double n0 = n[0], n1 = n[1], n2 = n[2];
+                    const double rho = (n0 * e0 + n1 * e1) + n2 * e2;
+                    e0 = rho * n0;
+                    e1 = rho * n1;
+                    e2 = rho * n2;
+                }
                 acc[0] += e0;
                 acc[1] += e1;
                 acc[2] += e2;

@@ -33,7 +33,9 @@ __global__ __launch_bounds__(kSvgdThreads) void grad_bandwidth_kernel(GradArgs g
         return;
     }
     const int64_t wg = (int64_t)blockIdx.x - bw_blocks;
-    const int grp = threadIdx.x / kGradThreads, lt = threadIdx.x % kGradThreads;
+    // the group (and so the particle and pair) is uniform over a wavefront:
+    // say so, and the pair's descriptor lives in scalar registers
+    const int grp = uniform(threadIdx.x / kGradThreads), lt = threadIdx.x % kGradThreads;
     grad_group(g, wg * kGradGroups + grp, (int64_t)n_pairs * v.K, grp, lt, lds);
 }
 

@@ -17,6 +17,7 @@
 #include "grad_bw.hpp"
 #include "nn.hpp"
 #include "nn_bf16_launch.h"
+#include "normals.hpp"
 #include "prep.hpp"
 #include "svgd.hpp"
 
@@ -174,6 +175,7 @@ struct stein_icp_ctx {
     float4* queries = nullptr;   // FP32 queries of the coming iteration, K*m per pair
     uint4* apack = nullptr;      // BF16 reference fragments (BF16 screen only)
     int32_t* match = nullptr;
+    double* nrm = nullptr;       // point-to-plane: (n, 0) per packed reference, FP64
     double* dscr = nullptr;
     int* flag = nullptr;
 
@@ -249,6 +251,9 @@ int validate_config(const stein_icp_config* c)
     if (c->n_scale < 0) return fail(STEIN_ICP_E_INVALID, "n_scale must be >= 0");
     if (c->use_graph != 0 && c->use_graph != 1) return fail(STEIN_ICP_E_INVALID, "use_graph must be 0 or 1");
     if (c->autotune != 0 && c->autotune != 1) return fail(STEIN_ICP_E_INVALID, "autotune must be 0 or 1");
+    if (c->metric != STEIN_ICP_METRIC_POINT && c->metric != STEIN_ICP_METRIC_PLANE)
+        return fail(STEIN_ICP_E_INVALID, "unknown metric");
+    if (c->normal_k < 3 || c->normal_k > kKnnMax) return fail(STEIN_ICP_E_INVALID, "normal_k must be in [3, 32]");
     return STEIN_ICP_OK;
 }
 
@@ -417,6 +422,7 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
     g.partial = c->partial;
     g.match = c->match;
     g.gbar = c->gbar;
+    g.nrm = c->cfg.metric == STEIN_ICP_METRIC_PLANE ? c->nrm : nullptr;
     g.K = c->K;
     g.m = c->m;
     g.rows = c->rows;
@@ -614,6 +620,59 @@ int autotune(stein_icp_ctx* c, hipStream_t s)
     return upload_tiling(c, s);
 }
 
+// The k nearest of n_ref references for nq queries (device float4 arrays)
+// and, if nrm is set, the normals of the neighbourhoods (nrm_stride doubles
+// per query; eig: optional eigenvalues). Scratch is allocated here and freed
+// after the stream has drained: an init-time call.
+int run_knn(const float4* q4, int64_t nq, const float4* ref4, int64_t n_ref, int32_t k, int32_t* idx, float* d2,
+            double* nrm, int32_t nrm_stride, double* eig, hipStream_t s)
+{
+    const int64_t qblocks = ceil_div(nq, kKnnThreads);
+    // about eight workgroups per compute unit, by splitting the references
+    int64_t chunks = std::max<int64_t>(1, ceil_div(8 * (int64_t)g_num_cus, qblocks));
+    chunks = std::min<int64_t>(chunks, ceil_div(n_ref, kKnnTile));
+    const int64_t chunk = round_up(ceil_div(n_ref, chunks), kKnnTile);
+    chunks = ceil_div(n_ref, chunk);
+    uint64_t* part = nullptr;
+    if (hipMalloc(&part, 8 * (size_t)chunks * (size_t)nq * (size_t)k) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(STEIN_ICP_E_NOMEM, "device allocation for the neighbour lists failed");
+    }
+    KnnArgs a{};
+    a.q4 = q4;
+    a.ref4 = ref4;
+    a.nq = nq;
+    a.n_ref = n_ref;
+    a.chunk = chunk;
+    a.partial = part;
+    a.k = k;
+    KnnMergeArgs b{};
+    b.partial = part;
+    b.ref4 = ref4;
+    b.nq = nq;
+    b.k = k;
+    b.chunks = (int32_t)chunks;
+    b.idx = idx;
+    b.d2 = d2;
+    b.nrm = nrm;
+    b.eig = eig;
+    b.nrm_stride = nrm_stride;
+    const dim3 grid((unsigned)qblocks, (unsigned)chunks);
+    if (k <= 16) {
+        hipLaunchKernelGGL(knn_partial_kernel<16>, grid, dim3(kKnnThreads), 0, s, a);
+        hipLaunchKernelGGL(knn_merge_kernel<16>, grid1d(nq, 256), dim3(256), 0, s, b);
+    } else {
+        hipLaunchKernelGGL(knn_partial_kernel<kKnnMax>, grid, dim3(kKnnThreads), 0, s, a);
+        hipLaunchKernelGGL(knn_merge_kernel<kKnnMax>, grid1d(nq, 256), dim3(256), 0, s, b);
+    }
+    hipError_t e = hipGetLastError();
+    const hipError_t e2 = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = e2;
+    (void)hipFree(part);
+    if (e != hipSuccess) return fail(STEIN_ICP_E_DEVICE, std::string("neighbour search: ") + hipGetErrorString(e));
+    return STEIN_ICP_OK;
+}
+
 void free_ctx(stein_icp_ctx* c)
 {
     if (!c) return;
@@ -723,6 +782,8 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     const size_t o_queries = take(sizeof(float4) * (size_t)P * nq);
     const size_t o_apack = take(sizeof(uint4) * (size_t)std::max<int64_t>(apack_n, 1));
     const size_t o_match = take(4 * (size_t)P * nq);
+    const bool plane = cfg->metric == STEIN_ICP_METRIC_PLANE;
+    const size_t o_nrm = take(plane ? 32 * (size_t)ro : 32);
     const size_t o_dscr = take(8 * (size_t)P * npairs2);
     const size_t o_flag = take(64);
     if (hipMalloc(&c->arena, off) != hipSuccess) {
@@ -748,6 +809,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     c->queries = (float4*)(c->arena + o_queries);
     c->apack = (uint4*)(c->arena + o_apack);
     c->match = (int32_t*)(c->arena + o_match);
+    c->nrm = (double*)(c->arena + o_nrm);
     c->dscr = (double*)(c->arena + o_dscr);
     c->flag = (int*)(c->arena + o_flag);
 
@@ -805,6 +867,13 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     if (flag & 1) return bail(fail(STEIN_ICP_E_INVALID, "a cloud holds a non-finite coordinate or one above 1e9"));
     if (flag & 2) return bail(fail(STEIN_ICP_E_INVALID, "a schedule index lies outside [0, n_src)"));
     if (flag & 4) return bail(fail(STEIN_ICP_E_INVALID, "an initial particle is non-finite"));
+    if (plane) {
+        for (const auto& pd : c->pairs) {
+            rc = run_knn(c->ref4 + pd.ref_off, pd.n_ref, c->ref4 + pd.ref_off, pd.n_ref, cfg->normal_k, nullptr,
+                         nullptr, c->nrm + 4 * pd.ref_off, 4, nullptr, s);
+            if (rc) return bail(rc);
+        }
+    }
     rc = upload_tiling(c, s);
     if (rc) return bail(rc);
     if (cfg->autotune) {
@@ -853,6 +922,8 @@ void stein_icp_default_config(stein_icp_config* c)
         c->prior_kappa_rot[i] = 0.0;
     }
     c->use_graph = 1;
+    c->metric = STEIN_ICP_METRIC_POINT;
+    c->normal_k = 10;
 }
 
 const char* stein_icp_last_error(void) { return g_err.c_str(); }
@@ -1138,6 +1209,83 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     if (e != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, std::string("stein_icp_nn: ") + hipGetErrorString(e));
     (void)hipFree(mem);
     return rc;
+}
+
+namespace {
+
+// Pack device xyz clouds into float4 scratch, check them, and run the
+// neighbour search (and normals) over them. q_xyz == NULL: the queries are
+// the references themselves.
+int knn_entry(const char* fn, const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n_ref, int32_t k,
+              int32_t* idx, float* d2, double* nrm, double* eig, hipStream_t s)
+{
+    const int64_t nq_pad = round_up(std::max<int64_t>(nq, 1), 64), nr_pad = round_up(n_ref, 64);
+    char* mem = nullptr;
+    const size_t o_r = 16 * (size_t)nq_pad, bytes = o_r + 16 * (size_t)nr_pad + 256;
+    if (hipMalloc(&mem, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(STEIN_ICP_E_NOMEM, std::string(fn) + ": device allocation failed");
+    }
+    float4* q4 = (float4*)mem;
+    float4* r4 = (float4*)(mem + o_r);
+    int* fl = (int*)(mem + o_r + 16 * (size_t)nr_pad);
+    int flag = 0, rc = STEIN_ICP_OK;
+    hipError_t e = hipMemsetAsync(fl, 0, sizeof(int), s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(pack_points_kernel, grid1d(n_ref, 256), dim3(256), 0, s, ref_xyz, n_ref, n_ref, r4, fl);
+        if (q_xyz)
+            hipLaunchKernelGGL(pack_points_kernel, grid1d(nq, 256), dim3(256), 0, s, q_xyz, nq, nq, q4, fl);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, fl, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        rc = fail(STEIN_ICP_E_DEVICE, std::string(fn) + ": " + hipGetErrorString(e));
+    else if (flag)
+        rc = fail(STEIN_ICP_E_INVALID, std::string(fn) + ": a coordinate is non-finite or above 1e9");
+    else
+        rc = run_knn(q_xyz ? q4 : r4, nq, r4, n_ref, k, idx, d2, nrm, 3, eig, s);
+    (void)hipFree(mem);
+    return rc;
+}
+
+}  // namespace
+
+int stein_icp_knn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n_ref, int32_t k, int32_t* idx,
+                  float* d2, void* hip_stream)
+{
+    if (nq < 0 || n_ref < 1) return fail(STEIN_ICP_E_INVALID, "need nq >= 0 and n_ref >= 1");
+    if (nq > kMaxRef || n_ref > kMaxRef) return fail(STEIN_ICP_E_INVALID, "sizes must be below 2^31 - 64");
+    if (k < 1 || k > kKnnMax) return fail(STEIN_ICP_E_INVALID, "k must be in [1, 32]");
+    if (nq == 0) return STEIN_ICP_OK;
+    if (!q_xyz || !ref_xyz || !idx || !d2) return fail(STEIN_ICP_E_INVALID, "a pointer is NULL");
+    return knn_entry("stein_icp_knn", q_xyz, nq, ref_xyz, n_ref, k, idx, d2, nullptr, nullptr,
+                     (hipStream_t)hip_stream);
+}
+
+int stein_icp_normals(const float* ref_xyz, int64_t n_ref, int32_t k, double* normals, double* eig, void* hip_stream)
+{
+    if (n_ref < 1 || n_ref > kMaxRef) return fail(STEIN_ICP_E_INVALID, "n_ref must be in [1, 2^31 - 64)");
+    if (k < 3 || k > kKnnMax) return fail(STEIN_ICP_E_INVALID, "k must be in [3, 32]");
+    if (!ref_xyz || !normals) return fail(STEIN_ICP_E_INVALID, "a pointer is NULL");
+    return knn_entry("stein_icp_normals", nullptr, n_ref, ref_xyz, n_ref, k,
+                     nullptr, nullptr, normals, eig, (hipStream_t)hip_stream);
+}
+
+int stein_icp_get_normals(const stein_icp_ctx* ctx, double* out, void* hip_stream)
+{
+    if (!ctx || !out) return fail(STEIN_ICP_E_INVALID, "ctx or out is NULL");
+    if (ctx->cfg.metric != STEIN_ICP_METRIC_PLANE)
+        return fail(STEIN_ICP_E_STATE, "the context uses the point-to-point metric: it holds no normals");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int64_t o = 0;
+    for (const auto& pd : ctx->pairs) {
+        if (hipMemcpy2DAsync(out + 3 * o, 3 * sizeof(double), ctx->nrm + 4 * pd.ref_off, 4 * sizeof(double),
+                             3 * sizeof(double), (size_t)pd.n_ref, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return fail(STEIN_ICP_E_DEVICE, "copying the normals failed");
+        o += pd.n_ref;
+    }
+    return STEIN_ICP_OK;
 }
 
 int stein_icp_make_schedule(uint64_t seed, int64_t n_src, int32_t m, int32_t rows, int32_t* out_host)

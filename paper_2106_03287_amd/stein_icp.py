@@ -17,6 +17,7 @@ NN_FP32, NN_BF16_RERANK = 0, 1
 OPT_ADAM, OPT_SGD = 0, 1
 BW_MEDIAN, BW_FIXED = 0, 1
 PRIOR_UNIFORM, PRIOR_GAUSS_VONMISES = 0, 1
+METRIC_POINT, METRIC_PLANE = 0, 1
 
 
 class SteinICPError(RuntimeError):
@@ -51,6 +52,8 @@ class stein_icp_config(C.Structure):
         ("n_scale", C.c_int64),
         ("use_graph", C.c_int32),
         ("autotune", C.c_int32),
+        ("metric", C.c_int32),
+        ("normal_k", C.c_int32),
     ]
 
 
@@ -61,6 +64,7 @@ EXPORTS = [
     "stein_icp_stage_times", "stein_icp_time_nn",
     "stein_icp_destroy",
     "stein_icp_last_error", "stein_icp_nn", "stein_icp_make_schedule", "stein_icp_make_init",
+    "stein_icp_knn", "stein_icp_normals", "stein_icp_get_normals",
 ]
 
 _lib = None
@@ -98,6 +102,9 @@ def lib():
     L.stein_icp_last_error.argtypes = []
     L.stein_icp_last_error.restype = C.c_char_p
     L.stein_icp_nn.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
+    L.stein_icp_knn.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
+    L.stein_icp_normals.argtypes = [vp, i64, i32, vp, vp, vp]
+    L.stein_icp_get_normals.argtypes = [vp, vp, vp]
     L.stein_icp_make_schedule.argtypes = [u64, i64, i32, i32, vp]
     L.stein_icp_make_init.argtypes = [u64, i32, dbl, dbl, vp, vp]
     for name in EXPORTS:
@@ -309,6 +316,34 @@ def stein_icp_nn(q, ref, mode=NN_FP32, stream=None):
     return idx, d2
 
 
+def stein_icp_knn(q, ref, k, stream=None):
+    import torch
+    _need(q, torch.float32, (q.shape[0], 3), "q")
+    _need(ref, torch.float32, (ref.shape[0], 3), "ref")
+    idx = torch.empty((q.shape[0], k), dtype=torch.int32, device=q.device)
+    d2 = torch.empty((q.shape[0], k), dtype=torch.float32, device=q.device)
+    _check("stein_icp_knn", lib().stein_icp_knn(_ptr(q), q.shape[0], _ptr(ref), ref.shape[0], int(k),
+                                                _ptr(idx), _ptr(d2), _stream(stream)))
+    return idx, d2
+
+
+def stein_icp_normals(ref, k, eig=False, stream=None):
+    import torch
+    _need(ref, torch.float32, (ref.shape[0], 3), "ref")
+    n = torch.empty((ref.shape[0], 3), dtype=torch.float64, device=ref.device)
+    w = torch.empty((ref.shape[0], 3), dtype=torch.float64, device=ref.device) if eig else None
+    _check("stein_icp_normals", lib().stein_icp_normals(_ptr(ref), ref.shape[0], int(k), _ptr(n), _ptr(w),
+                                                        _stream(stream)))
+    return (n, w) if eig else n
+
+
+def stein_icp_get_normals(ctx, n_total, stream=None):
+    import torch
+    out = torch.empty((n_total, 3), dtype=torch.float64, device="cuda")
+    _check("stein_icp_get_normals", lib().stein_icp_get_normals(ctx, _ptr(out), _stream(stream)))
+    return out
+
+
 def stein_icp_make_schedule(seed, n_src, m, rows):
     import numpy as np
     out = np.empty((rows, m), dtype=np.int32)
@@ -363,6 +398,9 @@ class SteinICP:
 
     def stage_times(self, n_iters):
         return stein_icp_stage_times(self.ctx, n_iters)
+
+    def normals(self, n_total):
+        return stein_icp_get_normals(self.ctx, n_total)
 
     def time_nn(self, n_launches):
         return stein_icp_time_nn(self.ctx, n_launches)

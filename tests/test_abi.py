@@ -39,6 +39,7 @@ def test_config_layout_and_defaults_follow_the_paper():
     assert (cfg.beta1, cfg.beta2, cfg.eps) == (0.9, 0.999, 1e-8)
     assert cfg.bandwidth_mode == S.BW_MEDIAN and cfg.prior_mode == S.PRIOR_UNIFORM
     assert cfg.optimizer == S.OPT_ADAM and cfg.nn_mode == S.NN_FP32
+    assert cfg.metric == S.METRIC_POINT and cfg.normal_k == 10
 
 
 def _init_rc(cfg, n_src=100, n_ref=100, src=1, ref=1):
@@ -64,6 +65,9 @@ def _init_rc(cfg, n_src=100, n_ref=100, src=1, ref=1):
     ("n_scale", -5, "n_scale"),
     ("use_graph", 2, "use_graph"),
     ("init_half_rot", float("inf"), "half"),
+    ("metric", 2, "metric"),
+    ("normal_k", 2, "normal_k"),
+    ("normal_k", 33, "normal_k"),
 ])
 def test_invalid_config_is_rejected_before_any_device_call(field, value, msg):
     cfg = S.stein_icp_default_config(batch_size=10)
@@ -92,6 +96,18 @@ def test_invalid_arguments_are_rejected():
     assert S.lib().stein_icp_step(None, 1, None) == S.E_INVALID
     assert S.lib().stein_icp_particles(None, None, None) == S.E_INVALID
     assert S.lib().stein_icp_nn(None, 1, None, 1, 0, None, None, None) == S.E_INVALID
+    fake = C.c_void_p(0x1000)   # never dereferenced: validation fails first
+    for k in (0, 33):
+        assert S.lib().stein_icp_knn(fake, 4, fake, 4, k, fake, fake, None) == S.E_INVALID
+        assert "k must be" in S.stein_icp_last_error()
+    assert S.lib().stein_icp_knn(fake, 4, fake, 4, 4, fake, None, None) == S.E_INVALID
+    assert S.lib().stein_icp_knn(fake, 4, fake, 0, 4, fake, fake, None) == S.E_INVALID
+    assert S.lib().stein_icp_knn(fake, 0, fake, 4, 4, fake, fake, None) == S.OK   # nothing to do
+    for k in (2, 33):
+        assert S.lib().stein_icp_normals(fake, 10, k, fake, None, None) == S.E_INVALID
+    assert S.lib().stein_icp_normals(fake, 0, 10, fake, None, None) == S.E_INVALID
+    assert S.lib().stein_icp_normals(fake, 10, 10, None, None, None) == S.E_INVALID
+    assert S.lib().stein_icp_get_normals(None, fake, None) == S.E_INVALID
     S.lib().stein_icp_destroy(None)
 
 

@@ -1,0 +1,246 @@
+"""GPU parity of the point-to-plane metric, through the C ABI, against the
+FP64 oracle on the same seeded clouds, particles and schedules.
+
+Bars: the k nearest neighbours (indices and FP32 distances) bit-exact, both
+sides deciding in FP32; the neighbourhood covariance is formed with the same
+FP64 operations on both sides, so the eigenvalues agree to the eigensolvers'
+accuracy (1e-12 of the trace) and a normal to 1e-13 divided by its relative
+eigengap (the smallest eigenvalue's distance to the middle one over the
+trace: the conditioning of an eigenvector), up to its sign, which is not
+defined; one iteration within the point-to-point bars; poses within
+1e-4 m / 1e-4 rad after the fixed iteration count."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_2106_03287_amd import stein_icp as S
+
+pytestmark = pytest.mark.gpu
+
+POSE_TOL = 1e-4
+STEP_RTOL = 1e-9
+K_NORMAL = 10
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def wrapped(d):
+    d = np.array(d, dtype=np.float64, copy=True)
+    d[..., 3:] = np.angle(np.exp(1j * d[..., 3:]))
+    return d
+
+
+def configs(prob, k=K_NORMAL, **extra):
+    g = dict(num_particles=prob.K, batch_size=prob.m, schedule_rows=prob.schedule.shape[0], lr=prob.lr,
+             metric=S.METRIC_PLANE, normal_k=k)
+    g.update(extra)
+    gcfg = S.stein_icp_default_config(**g)
+    ocfg = oracle.make_config(prob.K, prob.m, len(prob.pair.src), len(prob.pair.ref), lr=prob.lr,
+                              metric=oracle.PLANE)
+    return gcfg, ocfg
+
+
+def solver(prob, k=K_NORMAL, **extra):
+    gcfg, _ = configs(prob, k, **extra)
+    return S.SteinICP(gcfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule))
+
+
+def gpu_run(prob, T, k=K_NORMAL, **extra):
+    sol = solver(prob, k, **extra)
+    sol.step(T)
+    out = sol.particles().cpu().numpy()[0]
+    sol.close()
+    return out
+
+
+def oracle_run(prob, T, k=K_NORMAL):
+    _, ocfg = configs(prob, k)
+    nrm, _ = oracle.normals(prob.pair.ref, k)
+    st = oracle.State(prob.theta0)
+    oracle.run(ocfg, prob.pair.src, prob.pair.ref, prob.schedule, T, st, normals=nrm)
+    return st.theta
+
+
+def assert_poses_close(gpu, ref, tol=POSE_TOL):
+    d = np.abs(wrapped(gpu - ref))
+    print(f"max |dtheta| trans {d[:, :3].max():.3e} rot {d[:, 3:].max():.3e}", flush=True)
+    assert d.max() <= tol
+
+
+def assert_normals_match(n_gpu, w_gpu, n_or, w_or):
+    tr = w_or.sum(axis=1)
+    np.testing.assert_allclose(w_gpu, w_or, rtol=0, atol=1e-12 * tr.max())
+    np.testing.assert_allclose(w_gpu.sum(1), tr, rtol=1e-12, atol=1e-300)
+    relgap = (w_or[:, 1] - w_or[:, 0]) / np.where(tr > 0, tr, 1.0)
+    defined = np.any(n_or != 0, axis=1)
+    near_rule = np.abs(relgap - 1e-10) < 1e-11      # either side may decide the threshold
+    np.testing.assert_array_equal(np.any(n_gpu != 0, axis=1)[~near_rule], defined[~near_rule])
+    ok = defined & ~near_rule
+    np.testing.assert_allclose(np.linalg.norm(n_gpu[ok], axis=1), 1.0, atol=1e-14)
+    err = np.linalg.norm(np.cross(n_gpu[ok], n_or[ok]), axis=1)     # sine of the angle, sign-free
+    bound = 1e-13 / relgap[ok] + 1e-14
+    worst = np.max(err / bound) if ok.any() else 0.0
+    print(f"normals: {ok.sum()} defined, {(~defined).sum()} zero, worst error / bound {worst:.3f}", flush=True)
+    assert np.all(err <= bound)
+
+
+# ------------------------------------------------------------------ k nearest neighbours
+
+@pytest.mark.parametrize("nq,M,k", [(1, 1, 1), (300, 17, 10), (5, 3, 8), (4097, 2000, 10), (777, 20011, 32),
+                                    (2000, 70001, 16), (1500, 5000, 17), (0, 5, 4)])
+def test_knn_bitwise_against_oracle(nq, M, k):
+    rng = np.random.default_rng(nq * 13 + M + k)
+    ref = rng.uniform(-1, 1, (M, 3)).astype(np.float32)
+    q = rng.uniform(-1.2, 1.2, (nq, 3)).astype(np.float32)
+    if nq > 10 and M > 10:
+        q[:5] = ref[rng.integers(0, M, 5)]
+    print(f"knn nq={nq} M={M} k={k}", flush=True)
+    idx, d2 = S.stein_icp_knn(dev(q).reshape(-1, 3), dev(ref), k)
+    if nq == 0:
+        return
+    oi, od = oracle.knn_f32(q, ref, k)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    np.testing.assert_array_equal(d2.cpu().numpy(), od)
+
+
+@pytest.mark.parametrize("k", [10, 32])
+def test_knn_exact_ties_take_the_lowest_indices(k):
+    rng = np.random.default_rng(5 + k)
+    ref = rng.integers(-4, 5, (3001, 3)).astype(np.float32)
+    q = rng.integers(-5, 6, (1200, 3)).astype(np.float32)
+    idx, d2 = S.stein_icp_knn(dev(q), dev(ref), k)
+    oi, od = oracle.knn_f32(q, ref, k)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    np.testing.assert_array_equal(d2.cpu().numpy(), od)
+
+
+# ------------------------------------------------------------------ normals
+
+@pytest.mark.parametrize("name,k", [("cuboid", 3), ("cuboid", 10), ("cuboid", 32), ("kinect", 10)])
+def test_normals_against_oracle(name, k):
+    ref = synth.make_problem(name, 0, T=1).pair.ref
+    print(f"normals {name} M={len(ref)} k={k}", flush=True)
+    n, w = S.stein_icp_normals(dev(ref), k, eig=True)
+    n_or, w_or = oracle.normals(ref, k)
+    assert_normals_match(n.cpu().numpy(), w.cpu().numpy(), n_or, w_or)
+
+
+def test_normals_full_lidar_reference():
+    ref = synth.make_problem("lidar", 0, K=1, T=1).pair.ref
+    print(f"normals lidar M={len(ref)} k={K_NORMAL}", flush=True)
+    n, w = S.stein_icp_normals(dev(ref), K_NORMAL, eig=True)
+    n_or, w_or = oracle.normals(ref, K_NORMAL)
+    assert_normals_match(n.cpu().numpy(), w.cpu().numpy(), n_or, w_or)
+
+
+def test_normals_of_degenerate_and_exact_neighbourhoods():
+    t = np.arange(40) / 16.0
+    line = np.column_stack([t, 2 * t, -t]).astype(np.float32)
+    same = np.tile(np.array([[0.5, -0.25, 2.0]], np.float32), (20, 1))
+    star = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.float32)
+    g = np.arange(-16, 17) / 64.0
+    x, y = np.meshgrid(g, g)
+    plane = np.column_stack([x.ravel(), y.ravel(), 0.25 * x.ravel() + 0.5 * y.ravel() + 0.125]).astype(np.float32)
+    few = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]], np.float32)
+    for cloud, k in ((line, 8), (same, 8), (star, 7), (plane, 10), (few, 10)):
+        n, w = S.stein_icp_normals(dev(cloud), k, eig=True)
+        n, w = n.cpu().numpy(), w.cpu().numpy()
+        n_or, w_or = oracle.normals(cloud, k)
+        np.testing.assert_array_equal(np.any(n != 0, axis=1), np.any(n_or != 0, axis=1))
+        np.testing.assert_allclose(np.abs(np.einsum("ij,ij->i", n, n_or)), np.abs(np.einsum("ij,ij->i", n_or, n_or)),
+                                   atol=1e-12)
+    n = S.stein_icp_normals(dev(plane), 10).cpu().numpy()
+    true = np.array([-0.25, -0.5, 1.0]) / np.sqrt(1.3125)
+    np.testing.assert_allclose(np.abs(n @ true), 1.0, atol=1e-12)
+
+
+# ------------------------------------------------------------------ the solver
+
+def _one_step(prob):
+    sol = solver(prob)
+    sol.step(1)
+    diag = {k: v.cpu().numpy()[0] for k, v in sol.diagnostics().items()}
+    th = sol.particles().cpu().numpy()[0]
+    sol.close()
+    _, ocfg = configs(prob)
+    nrm, _ = oracle.normals(prob.pair.ref, K_NORMAL)
+    st = oracle.State(prob.theta0)
+    od = oracle.step(ocfg, prob.pair.src, prob.pair.ref, prob.schedule[0], st, normals=nrm)
+    np.testing.assert_array_equal(diag["match"], od["match"])
+    scale_g = np.abs(od["gbar"]).max()
+    np.testing.assert_allclose(diag["gbar"], od["gbar"], rtol=STEP_RTOL, atol=1e-12 * scale_g)
+    np.testing.assert_allclose(diag["h"], od["h"], rtol=1e-12)
+    scale = np.abs(od["phi"]).max()
+    np.testing.assert_allclose(diag["phi"], od["phi"], rtol=STEP_RTOL, atol=1e-12 * scale)
+    np.testing.assert_allclose(th, st.theta, rtol=0, atol=1e-11)
+
+
+def test_plane_one_iteration_cuboid():
+    _one_step(synth.make_problem("cuboid", 0))
+
+
+def test_plane_one_iteration_kinect():
+    _one_step(synth.make_problem("kinect", 0, T=1))
+
+
+def test_plane_one_iteration_lidar_full_size():
+    print("lidar full-size point-to-plane iteration: K=300 m=1000 M=100000", flush=True)
+    _one_step(synth.make_problem("lidar", 0, T=1))
+
+
+def test_plane_cuboid_50_iterations_free_running():
+    prob = synth.make_problem("cuboid", 0)
+    assert_poses_close(gpu_run(prob, prob.T), oracle_run(prob, prob.T))
+
+
+def test_plane_kinect_20_iterations_free_running():
+    prob = synth.make_problem("kinect", 1, T=20)
+    assert_poses_close(gpu_run(prob, 20), oracle_run(prob, 20))
+
+
+def test_plane_ragged_sizes_and_small_k():
+    prob = synth.make_problem("cuboid", 5, K=33, m=37, T=8, pair=synth.cuboid_pair(77, n_src=301, n_ref=1003))
+    assert_poses_close(gpu_run(prob, 8, k=3), oracle_run(prob, 8, k=3))
+
+
+def test_plane_context_normals_batched_and_graphs_agree_bitwise():
+    probs = [synth.make_problem("cuboid", 20 + i, K=16, m=40, T=6,
+                                pair=synth.cuboid_pair(950 + i, n_src=n, n_ref=M))
+             for i, (n, M) in enumerate([(300, 1000), (500, 2003), (64, 77)])]
+    gcfg, _ = configs(probs[0])
+    batch = S.SteinICP.batch(gcfg, [dev(p.pair.src) for p in probs], [dev(p.pair.ref) for p in probs],
+                             dev(np.stack([p.theta0 for p in probs])), [dev(p.schedule) for p in probs])
+    total = sum(len(p.pair.ref) for p in probs)
+    nb = batch.normals(total).cpu().numpy()
+    batch.step(6)
+    got = batch.particles().cpu().numpy()
+    batch.close()
+    o = 0
+    for i, p in enumerate(probs):
+        alone = S.stein_icp_normals(dev(p.pair.ref), K_NORMAL).cpu().numpy()
+        np.testing.assert_array_equal(nb[o:o + len(p.pair.ref)], alone)
+        o += len(p.pair.ref)
+        single = gpu_run(p, 6)
+        np.testing.assert_array_equal(got[i], single)
+        np.testing.assert_array_equal(single, gpu_run(p, 6, use_graph=0))
+        assert_poses_close(got[i], oracle_run(p, 6))
+
+
+def test_plane_with_the_certified_bf16_search_equals_fp32_bitwise():
+    prob = synth.make_problem("kinect", 2, T=30)
+    a = gpu_run(prob, 30)
+    b = gpu_run(prob, 30, nn_mode=S.NN_BF16_RERANK)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_point_to_point_context_holds_no_normals():
+    prob = synth.make_problem("cuboid", 0, T=1)
+    cfg = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m)
+    sol = S.SteinICP(cfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule))
+    with pytest.raises(S.SteinICPError, match="point-to-point"):
+        sol.normals(len(prob.pair.ref))
+    sol.close()
