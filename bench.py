@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Stein-ICP iters/s & particle·point NN queries/s; time-to-MMD≤0.05 vs plain"
 VALU_PEAK_TFLOPS = 157.3    # MI355X FP32 vector peak: 256 CUs x 2.4 GHz x 256 FP32 flop/clk/CU
 MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
+NORMAL_K = 10               # neighbours per normal of the point-to-plane metric
 FLOPS_PER_PAIR = 9          # 3 sub + 3 mul + 2 add (squared distance) + 1 compare
 NN_SOURCES = ["paper_2106_03287_amd/csrc/nn.hpp", "paper_2106_03287_amd/csrc/common.hpp"]
 NN_BF16_SOURCES = NN_SOURCES + ["paper_2106_03287_amd/csrc/nn_bf16.hpp"]
@@ -51,24 +52,28 @@ def measured_traffic(workload, tiling, nn="fp32"):
     return rec["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(prob, budget_s=15.0):
+def cpu_baseline(prob, budget_s=15.0, plane=False):
     """The FP64 oracle as it stands, on this host's cores, for as many of the
-    workload's iterations as fit in about ``budget_s`` seconds."""
+    workload's iterations as fit in about ``budget_s`` seconds (point-to-plane:
+    the normals are computed first, outside the timing, as at init)."""
     import oracle
-    cfg = oracle.make_config(prob.K, prob.m, len(prob.pair.src), len(prob.pair.ref), lr=prob.lr)
+    cfg = oracle.make_config(prob.K, prob.m, len(prob.pair.src), len(prob.pair.ref), lr=prob.lr,
+                             metric=oracle.PLANE if plane else oracle.POINT)
+    nrm = oracle.normals(prob.pair.ref, NORMAL_K)[0] if plane else None
     st = oracle.State(prob.theta0)
-    oracle.run(cfg, prob.pair.src, prob.pair.ref, prob.schedule, 1, st)  # warm-up / estimate
+    oracle.run(cfg, prob.pair.src, prob.pair.ref, prob.schedule, 1, st, normals=nrm)  # warm-up / estimate
     t0 = time.perf_counter()
-    oracle.run(cfg, prob.pair.src, prob.pair.ref, prob.schedule, 1, st)
+    oracle.run(cfg, prob.pair.src, prob.pair.ref, prob.schedule, 1, st, normals=nrm)
     per = time.perf_counter() - t0
     n = int(max(1, min(prob.T - 2, budget_s / max(per, 1e-6))))
     t0 = time.perf_counter()
-    oracle.run(cfg, prob.pair.src, prob.pair.ref, prob.schedule, n, st)
+    oracle.run(cfg, prob.pair.src, prob.pair.ref, prob.schedule, n, st, normals=nrm)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": (n + 1) / (dt + per), "unit": "iters/s", "cores": cores, "kind": "oracle",
             "sample": f"iterations 2-{n + 2} of the {prob.name} workload (pair 0, K={prob.K}, "
-                      f"m={prob.m}, M={len(prob.pair.ref)}), FP64 oracle with OpenMP NN"}
+                      f"m={prob.m}, M={len(prob.pair.ref)}{', point-to-plane' if plane else ''}), "
+                      f"FP64 oracle with OpenMP NN"}
 
 
 # NN shapes (queries per lane, wavefronts per workgroup, chunk, persistent
@@ -100,6 +105,8 @@ def main():
     ap.add_argument("--nn", default="auto", choices=["auto", "fp32", "bf16"],
                     help="nearest-neighbour search: FP32, or the certified BF16 matrix-core screen (the same "
                          "answers); auto takes the faster for the workload")
+    ap.add_argument("--metric", default="point", choices=["point", "plane"],
+                    help="ICP error metric: point-to-point (Eqs. 4-5) or point-to-plane (normals at init)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", type=int, default=0,
                     help="tune the NN shape at init instead of using the pinned shape of the workload")
@@ -148,10 +155,25 @@ def main():
     cfg = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m,
                                      schedule_rows=prob.schedule.shape[0], lr=prob.lr,
                                      autotune=0 if args.tiling else args.autotune,
-                                     nn_mode=S.NN_BF16_RERANK if args.nn == "bf16" else S.NN_FP32)
+                                     nn_mode=S.NN_BF16_RERANK if args.nn == "bf16" else S.NN_FP32,
+                                     metric=S.METRIC_PLANE if args.metric == "plane" else S.METRIC_POINT,
+                                     normal_k=NORMAL_K)
     t_init = time.perf_counter()
     sol = S.SteinICP(cfg, src, ref, theta0, sched)
     init_ms = (time.perf_counter() - t_init) * 1e3
+    normals_ms = None
+    if args.metric == "plane":
+        # the init-time normals alone (k nearest neighbours of every reference
+        # point and their PCA), standalone call, median of 5
+        S.stein_icp_normals(ref, NORMAL_K)
+        ts = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            S.stein_icp_normals(ref, NORMAL_K)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t1) * 1e3)
+        normals_ms = float(np.median(ts))
     if args.tiling:
         sol.set_tiling(*[int(x) for x in args.tiling.split(",")])
     tiling = sol.tiling()
@@ -206,7 +228,8 @@ def main():
         sol.step(1)
         mb = sol.diagnostics()["match"]
         cfg32 = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m,
-                                           schedule_rows=prob.schedule.shape[0], lr=prob.lr)
+                                           schedule_rows=prob.schedule.shape[0], lr=prob.lr,
+                                           metric=cfg.metric, normal_k=NORMAL_K)
         ref32 = S.SteinICP(cfg32, src, ref, theta0, sched)
         ref32.step(1)
         mismatch = float((mb != ref32.diagnostics()["match"]).double().mean().item())
@@ -231,12 +254,13 @@ def main():
         "dtype": "bf16+f32" if args.nn == "bf16" else "f32",
         "data": "synthetic",
         "config": {"workload": prob.name, "K": prob.K, "m": prob.m, "T": prob.T,
-                   "N": len(prob.pair.src), "M": M, "nn": args.nn,
+                   "N": len(prob.pair.src), "M": M, "nn": args.nn, "metric": args.metric,
                    "step": "one full solve of T iterations"},
         "nn_queries_per_s": round(queries_per_s, 1),
         "pair_evals_per_s": round(queries_per_s * M, 1),
         "stage_ms_per_iter": {k: round(v / prob.T, 5) for k, v in stage.items()},
         "init_ms": round(init_ms, 2),
+        "normals_ms": None if normals_ms is None else round(normals_ms, 3),
         "nn_tiling": tiling,
         "nn_mismatch_vs_fp32": mismatch,
         "particles_identical_to_fp32_solve": identical,
@@ -245,7 +269,7 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob)
+        out["cpu_baseline"] = cpu_baseline(prob, plane=args.metric == "plane")
     print(json.dumps(out), flush=True)
 
 
@@ -328,6 +352,7 @@ def run_batched(args):
         "batched_equals_sequential_bitwise": same,
         "stage_ms_per_iter": {k: round(v / T, 5) for k, v in stage.items()},
         "init_ms": round(init_ms, 2),
+        "normals_ms": None if normals_ms is None else round(normals_ms, 3),
         "nn_tiling": tiling,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,

@@ -4,7 +4,8 @@
 //
 // knn_partial_kernel: a workgroup takes 256 queries (one per thread) and one
 // chunk of the references, staged through LDS 256 at a time; every thread
-// keeps its k smallest (distance, index) keys in registers as a sorted list.
+// keeps its k smallest (distance, index) keys in registers as a sorted list,
+// screening 32 references at a time before inserting.
 // knn_merge_kernel: one thread per query merges the chunks' lists, writes the
 // neighbours and/or forms the FP64 covariance of the neighbourhood and its
 // normal.
@@ -65,11 +66,27 @@ __global__ __launch_bounds__(kKnnThreads) void knn_partial_kernel(KnnArgs a)
         if (j < j1) tile[threadIdx.x] = a.ref4[j];
         __syncthreads();
         const int n = j1 - t0 < kKnnTile ? (int)(j1 - t0) : kKnnTile;
-#pragma unroll 4
-        for (int u = 0; u < n; ++u) {
-            const float4 r = tile[u];
-            const uint64_t key = pack_key(dist2_f32(q.x, q.y, q.z, r.x, r.y, r.z), (uint32_t)(t0 + u));
-            if (key < b[KMAX - 1]) topk_insert(b, key);
+        for (int u0 = 0; u0 < n; u0 += 32) {
+            // screen 32 references against the list's current worst distance
+            // (a stale, so conservative, bound), then insert the lane's own
+            // survivors: the wavefront runs as many insertions as its busiest
+            // lane needs, not one for every reference some lane keeps
+            const uint64_t worst = b[KMAX - 1];
+            const float thr = worst == kNoKey ? __builtin_inff() : __uint_as_float((uint32_t)(worst >> 32));
+            uint32_t mask = 0;
+#pragma unroll
+            for (int u = 0; u < 32; ++u) {
+                const float4 r = tile[u0 + u];
+                const float d = dist2_f32(q.x, q.y, q.z, r.x, r.y, r.z);
+                if (u0 + u < n && d <= thr) mask |= 1u << u;
+            }
+            while (mask) {
+                const int u = __builtin_ctz(mask);
+                mask &= mask - 1;
+                const float4 r = tile[u0 + u];
+                const uint64_t key = pack_key(dist2_f32(q.x, q.y, q.z, r.x, r.y, r.z), (uint32_t)(t0 + u0 + u));
+                if (key < b[KMAX - 1]) topk_insert(b, key);
+            }
         }
     }
     if (!live) return;
