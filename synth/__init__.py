@@ -16,4 +16,4 @@ from .clouds import (  # noqa: F401
     minibatch_schedule,
     rng_streams,
 )
-from .workloads import WORKLOADS, Problem, make_problem, batched_problems  # noqa: F401
+from .workloads import WORKLOADS, Problem, make_problem, batched_problems, MonteCarlo, mc_problem  # noqa: F401

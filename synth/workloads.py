@@ -118,3 +118,34 @@ def generate_pair(spec: tuple[str, int]) -> tuple[str, int, Pair]:
     processes)."""
     kind, seed = spec
     return kind, seed, _generate(kind, seed)
+
+
+# ---------------------------------------------------------------------------
+# Monte-Carlo ground truth: independent single-particle runs on one pair
+# ---------------------------------------------------------------------------
+
+MC_SEED = 7_000_000
+MC_HALF_TRANS, MC_HALF_ROT = 1.0, 0.1745   # start box of the paper's Monte-Carlo runs (m, rad)
+
+
+@dataclass
+class MonteCarlo:
+    problem: Problem          # the workload's Stein-ICP problem on the same pair
+    runs: int
+    theta0: np.ndarray        # float64 (runs, 1, 6)
+    schedules: np.ndarray     # int32 (runs, T, m), one fresh stream per run
+
+
+def mc_problem(name: str, pair_index: int = 0, runs: int = 1000, *, K=None, m=None, T=None,
+               half_trans: float = MC_HALF_TRANS, half_rot: float = MC_HALF_ROT,
+               pair: Pair | None = None) -> MonteCarlo:
+    """``runs`` independent starts and minibatch streams for single-particle
+    runs on workload ``name``'s pair, uniform in the workload's init centre
+    +- (half_trans, half_rot). Run r uses seed MC_SEED + 100_000 c + r for
+    workload index c."""
+    prob = make_problem(name, pair_index, K=K, m=m, T=T, pair=pair)
+    centre = prob.extra["centre"]
+    base = MC_SEED + 100_000 * WORKLOADS[name]["index"]
+    theta0 = np.stack([init_particles(base + r, 1, half_trans, half_rot, centre) for r in range(runs)])
+    scheds = np.stack([minibatch_schedule(base + r, len(prob.pair.src), prob.m, prob.T) for r in range(runs)])
+    return MonteCarlo(prob, runs, theta0, scheds)
