@@ -136,7 +136,12 @@ int stein_icp_init(stein_icp_ctx **out, const stein_icp_config *cfg,
  * schedule_rows for all). Host arrays of n_pairs device pointers and sizes.
  * init_particles: device FP64 n_pairs x K x 6, or NULL (pair p draws from
  * cfg->seed + p). schedules: host array of n_pairs device pointers, or NULL
- * (pair p draws from cfg->seed + p). Blocking, like stein_icp_init. */
+ * (pair p draws from cfg->seed + p). 1 <= n_pairs <= 65535. Pairs given the
+ * same cloud (same device pointer and size) share one packed copy of it, its
+ * normals and its BF16 fragments; with K = 1 and one cloud pair repeated,
+ * the pairs are independent SGD-ICP runs (the paper's Monte-Carlo ground
+ * truth, Sec. V-A), each with its own start and minibatches. Blocking, like
+ * stein_icp_init. */
 int stein_icp_batch_init(stein_icp_ctx **out, const stein_icp_config *cfg, int32_t n_pairs,
                          const float *const *src_xyz, const int64_t *n_src,
                          const float *const *ref_xyz, const int64_t *n_ref,
@@ -242,6 +247,21 @@ int stein_icp_normals(const float *ref_xyz, int64_t n_ref, int32_t k, double *no
  * (sum of n_ref over its pairs) x 3, pairs in order. E_STATE for a
  * point-to-point context. Stream-ordered. */
 int stein_icp_get_normals(const stein_icp_ctx *ctx, double *out, void *hip_stream);
+
+/* Scores of a posterior sample set a (host FP64 na x 6 poses) against a
+ * reference sample set b (host FP64 nb x 6), e.g. a Monte-Carlo ground truth
+ * of independent SGD-ICP runs (a batch context with K = 1 whose pairs all
+ * share one cloud pair), as the paper scores its posteriors (Sec. V-A):
+ *   kl[0], kl[1]: KL(N_a || N_b) between the normal fits (sample mean,
+ *     covariance with an n - 1 denominator) of the translations and of the
+ *     rotations;
+ *   ovl[0..5]: overlapping coefficient, the integral of min(f_a, f_b), of the
+ *     normal fits of each coordinate (0: disjoint, 1: identical).
+ * Angles are first taken within pi of b's circular mean. Either output may
+ * be NULL. E_INVALID for fewer than 2 poses in a set, a non-finite sample or
+ * a covariance that is not positive definite. No device needed. */
+int stein_icp_posterior_scores(const double *a, int64_t na, const double *b, int64_t nb,
+                               double *kl, double *ovl);
 
 /* Host helpers (no device needed). The library's own generator is
  * SplitMix64 (Steele, Lea, Flood 2014): uniform doubles from the top 53 bits,

@@ -693,7 +693,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     *out = nullptr;
     int rc = validate_config(cfg);
     if (rc) return rc;
-    if (P < 1) return fail(STEIN_ICP_E_INVALID, "n_pairs must be >= 1");
+    if (P < 1 || P > 65535) return fail(STEIN_ICP_E_INVALID, "n_pairs must be in [1, 65535]");
     if (!src || !n_src || !ref || !n_ref) return fail(STEIN_ICP_E_INVALID, "cloud arrays are NULL");
     const int32_t K = cfg->num_particles, m = cfg->batch_size, rows = cfg->schedule_rows;
     for (int32_t p = 0; p < P; ++p) {
@@ -719,12 +719,24 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     c->rows = rows;
     c->nq = nq;
 
-    // layout
+    // layout. Pairs given the same device cloud (pointer and size) share one
+    // packed copy of it (and of its normals and BF16 fragments): many
+    // independent runs on one pair read one cached reference.
     int64_t so = 0, ro = 0;
+    std::map<std::pair<const float*, int64_t>, int32_t> src_owner, ref_owner;
+    std::vector<int32_t> own_src(P), own_ref(P);   // pair that packed the cloud
     for (int32_t p = 0; p < P; ++p) {
         PairDesc pd{};
-        pd.src_off = so;
-        pd.ref_off = ro;
+        const auto ks = std::make_pair(src[p], n_src[p]);
+        const auto kr = std::make_pair(ref[p], n_ref[p]);
+        const auto is = src_owner.find(ks);
+        const auto ir = ref_owner.find(kr);
+        own_src[p] = is == src_owner.end() ? p : is->second;
+        own_ref[p] = ir == ref_owner.end() ? p : ir->second;
+        if (own_src[p] == p) src_owner[ks] = p;
+        if (own_ref[p] == p) ref_owner[kr] = p;
+        pd.src_off = own_src[p] == p ? so : c->pairs[own_src[p]].src_off;
+        pd.ref_off = own_ref[p] == p ? ro : c->pairs[own_ref[p]].ref_off;
         pd.n_src = n_src[p];
         pd.n_ref = n_ref[p];
         pd.n_ref_pad = round_up(n_ref[p], kTile);
@@ -732,8 +744,8 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
         pd.n_scale = cfg->n_scale > 0 ? cfg->n_scale : n_src[p];
         pd.q_off = (int64_t)p * nq;
         pd.nq = nq;
-        so += pd.n_src;
-        ro += pd.n_ref_pad;
+        if (own_src[p] == p) so += pd.n_src;
+        if (own_ref[p] == p) ro += pd.n_ref_pad;
         c->pairs.push_back(pd);
     }
     c->tiling = default_tiling(c->pairs, nq);
@@ -752,6 +764,12 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
         std::vector<float> h;
         for (int32_t p = 0; p < P; ++p) {
             PairDesc& pd = c->pairs[p];
+            if (own_ref[p] != p) {
+                const PairDesc& o = c->pairs[own_ref[p]];
+                for (int i = 0; i < 4; ++i) pd.c0[i] = o.c0[i];
+                pd.apack_off = o.apack_off;
+                continue;
+            }
             h.resize((size_t)pd.n_ref * 3);
             if (hipMemcpy(h.data(), ref[p], 12 * (size_t)pd.n_ref, hipMemcpyDeviceToHost) != hipSuccess) {
                 delete c;
@@ -771,6 +789,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
         return o;
     };
     const size_t o_pairs = take(sizeof(PairDesc) * P);
+    const size_t o_upairs = take(sizeof(PairDesc) * P);   // the pairs that own their reference
     const size_t o_src = take(sizeof(float4) * so);
     const size_t o_ref = take(sizeof(float4) * ro);
     const size_t o_sched = take(sizeof(int32_t) * (size_t)P * rows * m);
@@ -823,10 +842,12 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     std::vector<double> hinit;
     for (int32_t p = 0; p < P; ++p) {
         const PairDesc& pd = c->pairs[p];
-        hipLaunchKernelGGL(pack_points_kernel, grid1d(pd.n_src, 256), dim3(256), 0, s, src[p], pd.n_src, pd.n_src,
-                           c->src4 + pd.src_off, c->flag);
-        hipLaunchKernelGGL(pack_points_kernel, grid1d(pd.n_ref_pad, 256), dim3(256), 0, s, ref[p], pd.n_ref,
-                           pd.n_ref_pad, c->ref4 + pd.ref_off, c->flag);
+        if (own_src[p] == p)
+            hipLaunchKernelGGL(pack_points_kernel, grid1d(pd.n_src, 256), dim3(256), 0, s, src[p], pd.n_src, pd.n_src,
+                               c->src4 + pd.src_off, c->flag);
+        if (own_ref[p] == p)
+            hipLaunchKernelGGL(pack_points_kernel, grid1d(pd.n_ref_pad, 256), dim3(256), 0, s, ref[p], pd.n_ref,
+                               pd.n_ref_pad, c->ref4 + pd.ref_off, c->flag);
         const int64_t ns = (int64_t)rows * m;
         if (sched) {
             hipLaunchKernelGGL(copy_schedule_kernel, grid1d(ns, 256), dim3(256), 0, s, sched[p], ns, pd.n_src,
@@ -854,10 +875,16 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     if (hipMemcpyAsync(c->d_pairs, c->pairs.data(), sizeof(PairDesc) * P, hipMemcpyHostToDevice, s) != hipSuccess)
         return bail(fail(STEIN_ICP_E_DEVICE, "pair table upload failed"));
     if (enqueue_queries(c, s) != hipSuccess) return bail(fail(STEIN_ICP_E_DEVICE, "query kernel launch failed"));
+    std::vector<PairDesc> uref;   // one descriptor per packed reference
+    for (int32_t p = 0; p < P; ++p)
+        if (own_ref[p] == p) uref.push_back(c->pairs[p]);
     if (bf16) {
         int64_t maxblk = 0;
-        for (const auto& pd : c->pairs) maxblk = std::max<int64_t>(maxblk, pd.n_ref_pad / kTile);
-        if (launch_pack_bf16(c->d_pairs, P, maxblk, c->ref4, c->apack, s) != hipSuccess)
+        for (const auto& pd : uref) maxblk = std::max<int64_t>(maxblk, pd.n_ref_pad / kTile);
+        PairDesc* d_upairs = (PairDesc*)(c->arena + o_upairs);
+        if (hipMemcpyAsync(d_upairs, uref.data(), sizeof(PairDesc) * uref.size(), hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            launch_pack_bf16(d_upairs, (int32_t)uref.size(), maxblk, c->ref4, c->apack, s) != hipSuccess)
             return bail(fail(STEIN_ICP_E_DEVICE, "BF16 packing launch failed"));
     }
     int flag = 0;
@@ -868,7 +895,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     if (flag & 2) return bail(fail(STEIN_ICP_E_INVALID, "a schedule index lies outside [0, n_src)"));
     if (flag & 4) return bail(fail(STEIN_ICP_E_INVALID, "an initial particle is non-finite"));
     if (plane) {
-        for (const auto& pd : c->pairs) {
+        for (const auto& pd : uref) {
             rc = run_knn(c->ref4 + pd.ref_off, pd.n_ref, c->ref4 + pd.ref_off, pd.n_ref, cfg->normal_k, nullptr,
                          nullptr, c->nrm + 4 * pd.ref_off, 4, nullptr, s);
             if (rc) return bail(rc);
@@ -1285,6 +1312,147 @@ int stein_icp_get_normals(const stein_icp_ctx* ctx, double* out, void* hip_strea
             return fail(STEIN_ICP_E_DEVICE, "copying the normals failed");
         o += pd.n_ref;
     }
+    return STEIN_ICP_OK;
+}
+
+namespace {
+
+double wrap_pi(double a) { return std::atan2(std::sin(a), std::cos(a)); }
+
+// Mean and covariance (n - 1 denominator) of columns d0 .. d0 + 2 of the
+// n x 6 rows x; with `centre`, each value v is first taken as
+// centre + wrap(v - centre) (angles).
+void fit3(const double* x, int64_t n, int d0, const double* centre, double mu[3], double S[9])
+{
+    auto val = [&](int64_t i, int d) {
+        const double v = x[6 * i + d0 + d];
+        return centre ? centre[d] + wrap_pi(v - centre[d]) : v;
+    };
+    for (int d = 0; d < 3; ++d) {
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) acc += val(i, d);
+        mu[d] = acc / (double)n;
+    }
+    for (int e = 0; e < 9; ++e) S[e] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double v[3];
+        for (int d = 0; d < 3; ++d) v[d] = val(i, d) - mu[d];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) S[3 * r + c] += v[r] * v[c];
+    }
+    for (int e = 0; e < 9; ++e) S[e] /= (double)(n - 1);
+}
+
+// Lower Cholesky factor of a symmetric 3x3 matrix; false unless positive definite.
+bool chol3(const double S[9], double L[9])
+{
+    for (int e = 0; e < 9; ++e) L[e] = 0.0;
+    for (int j = 0; j < 3; ++j) {
+        double d = S[4 * j];
+        for (int k = 0; k < j; ++k) d -= L[3 * j + k] * L[3 * j + k];
+        if (!(d > 0.0) || !std::isfinite(d)) return false;
+        L[4 * j] = std::sqrt(d);
+        for (int i = j + 1; i < 3; ++i) {
+            double v = S[3 * i + j];
+            for (int k = 0; k < j; ++k) v -= L[3 * i + k] * L[3 * j + k];
+            L[3 * i + j] = v / L[4 * j];
+        }
+    }
+    return true;
+}
+
+// Solve L y = b in place (forward substitution).
+void lsolve3(const double L[9], double b[3])
+{
+    for (int i = 0; i < 3; ++i) {
+        for (int k = 0; k < i; ++k) b[i] -= L[3 * i + k] * b[k];
+        b[i] /= L[4 * i];
+    }
+}
+
+// KL(N(ma, Sa) || N(mb, Sb)) = (tr(Sb^-1 Sa) + |Lb^-1 (mb - ma)|^2 - 3 + ln det Sb - ln det Sa) / 2,
+// with tr(Sb^-1 Sa) = |Lb^-1 La|_F^2 for Cholesky factors La, Lb.
+bool kl_gauss3(const double ma[3], const double Sa[9], const double mb[3], const double Sb[9], double* out)
+{
+    double La[9], Lb[9];
+    if (!chol3(Sa, La) || !chol3(Sb, Lb)) return false;
+    double tr = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double col[3] = {La[c], La[3 + c], La[6 + c]};
+        lsolve3(Lb, col);
+        tr += (col[0] * col[0] + col[1] * col[1]) + col[2] * col[2];
+    }
+    double z[3] = {mb[0] - ma[0], mb[1] - ma[1], mb[2] - ma[2]};
+    lsolve3(Lb, z);
+    const double maha = (z[0] * z[0] + z[1] * z[1]) + z[2] * z[2];
+    double ld = 0.0;
+    for (int j = 0; j < 3; ++j) ld += 2.0 * (std::log(Lb[4 * j]) - std::log(La[4 * j]));
+    *out = 0.5 * (tr + maha - 3.0 + ld);
+    return true;
+}
+
+// Overlapping coefficient, the integral of min(f1, f2), of two normal
+// densities: with s1 < s2 the narrower density is the smaller one outside
+// the two crossing points x1 < x2 (roots of ln f1 = ln f2) and the larger
+// one between them; equal widths cross once, at the midpoint.
+double ovl_normal(double m1, double s1, double m2, double s2)
+{
+    const double r2 = 1.4142135623730951;   // sqrt(2)
+    if (s1 > s2) {
+        std::swap(m1, m2);
+        std::swap(s1, s2);
+    }
+    const double a = 1.0 / (s1 * s1) - 1.0 / (s2 * s2);
+    if (!(a > 0.0)) return std::erfc(std::fabs(m1 - m2) / (2.0 * r2 * s1));
+    const double b = -2.0 * (m1 / (s1 * s1) - m2 / (s2 * s2));
+    const double c = (m1 * m1) / (s1 * s1) - (m2 * m2) / (s2 * s2) - 2.0 * std::log(s2 / s1);
+    const double disc = std::max(b * b - 4.0 * a * c, 0.0);
+    const double q = -0.5 * (b + (b >= 0.0 ? 1.0 : -1.0) * std::sqrt(disc));
+    double x1 = q / a, x2 = q != 0.0 ? c / q : x1;
+    if (x1 > x2) std::swap(x1, x2);
+    // tails of f1 beyond x1 and x2, and the mass of f2 between them
+    const double t1 = 0.5 * std::erfc((m1 - x1) / (r2 * s1));
+    const double t2 = 0.5 * std::erfc((x2 - m1) / (r2 * s1));
+    const double mid = 0.5 * (std::erfc((x1 - m2) / (r2 * s2)) - std::erfc((x2 - m2) / (r2 * s2)));
+    return t1 + mid + t2;
+}
+
+}  // namespace
+
+int stein_icp_posterior_scores(const double* a, int64_t na, const double* b, int64_t nb, double* kl, double* ovl)
+{
+    if (!a || !b) return fail(STEIN_ICP_E_INVALID, "a sample array is NULL");
+    if (na < 2 || nb < 2) return fail(STEIN_ICP_E_INVALID, "each sample set needs at least 2 poses");
+    for (int64_t i = 0; i < 6 * na; ++i)
+        if (!std::isfinite(a[i])) return fail(STEIN_ICP_E_INVALID, "a sample is non-finite");
+    for (int64_t i = 0; i < 6 * nb; ++i)
+        if (!std::isfinite(b[i])) return fail(STEIN_ICP_E_INVALID, "a sample is non-finite");
+    // angles around the circular mean of the reference set b
+    double centre[3];
+    for (int d = 0; d < 3; ++d) {
+        double sn = 0.0, cs = 0.0;
+        for (int64_t i = 0; i < nb; ++i) {
+            sn += std::sin(b[6 * i + 3 + d]);
+            cs += std::cos(b[6 * i + 3 + d]);
+        }
+        centre[d] = std::atan2(sn, cs);
+    }
+    double mu_a[2][3], S_a[2][9], mu_b[2][3], S_b[2][9];
+    for (int g = 0; g < 2; ++g) {
+        fit3(a, na, 3 * g, g ? centre : nullptr, mu_a[g], S_a[g]);
+        fit3(b, nb, 3 * g, g ? centre : nullptr, mu_b[g], S_b[g]);
+    }
+    double k[2], o[6];
+    for (int g = 0; g < 2; ++g)
+        if (!kl_gauss3(mu_a[g], S_a[g], mu_b[g], S_b[g], &k[g]))
+            return fail(STEIN_ICP_E_INVALID, "a sample covariance is not positive definite");
+    for (int g = 0; g < 2; ++g)
+        for (int d = 0; d < 3; ++d)
+            o[3 * g + d] = ovl_normal(mu_a[g][d], std::sqrt(S_a[g][4 * d]), mu_b[g][d], std::sqrt(S_b[g][4 * d]));
+    if (kl)
+        for (int g = 0; g < 2; ++g) kl[g] = k[g];
+    if (ovl)
+        for (int d = 0; d < 6; ++d) ovl[d] = o[d];
     return STEIN_ICP_OK;
 }
 

@@ -64,7 +64,7 @@ EXPORTS = [
     "stein_icp_stage_times", "stein_icp_time_nn",
     "stein_icp_destroy",
     "stein_icp_last_error", "stein_icp_nn", "stein_icp_make_schedule", "stein_icp_make_init",
-    "stein_icp_knn", "stein_icp_normals", "stein_icp_get_normals",
+    "stein_icp_knn", "stein_icp_normals", "stein_icp_get_normals", "stein_icp_posterior_scores",
 ]
 
 _lib = None
@@ -105,6 +105,7 @@ def lib():
     L.stein_icp_knn.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
     L.stein_icp_normals.argtypes = [vp, i64, i32, vp, vp, vp]
     L.stein_icp_get_normals.argtypes = [vp, vp, vp]
+    L.stein_icp_posterior_scores.argtypes = [vp, i64, vp, i64, vp, vp]
     L.stein_icp_make_schedule.argtypes = [u64, i64, i32, i32, vp]
     L.stein_icp_make_init.argtypes = [u64, i32, dbl, dbl, vp, vp]
     for name in EXPORTS:
@@ -342,6 +343,18 @@ def stein_icp_get_normals(ctx, n_total, stream=None):
     out = torch.empty((n_total, 3), dtype=torch.float64, device="cuda")
     _check("stein_icp_get_normals", lib().stein_icp_get_normals(ctx, _ptr(out), _stream(stream)))
     return out
+
+
+def stein_icp_posterior_scores(a, b):
+    """KL (translation, rotation) and per-coordinate OVL of pose samples a
+    against reference samples b (host FP64 arrays n x 6)."""
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1, 6)
+    b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1, 6)
+    kl, ovl = np.empty(2), np.empty(6)
+    _check("stein_icp_posterior_scores",
+           lib().stein_icp_posterior_scores(_ptr(a), len(a), _ptr(b), len(b), _ptr(kl), _ptr(ovl)))
+    return kl, ovl
 
 
 def stein_icp_make_schedule(seed, n_src, m, rows):
