@@ -83,7 +83,7 @@ def cpu_baseline(prob, budget_s=15.0, plane=False):
 # answers bit for bit; measured faster than the FP32 search on the Kinect
 # (1.25x on the NN stage) and LiDAR (1.37x) workloads, slower on the small
 # cuboid clouds, where the search is latency-bound
-AUTO_NN = {"cuboid": "fp32", "kinect": "bf16", "lidar": "bf16"}
+AUTO_NN = {"cuboid": "fp32", "kinect": "bf16", "lidar": "bf16", "mc": "bf16"}
 
 PINNED_TILING = {
     ("kinect", "fp32"): "4,16,2048,2",
@@ -98,7 +98,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="kinect", choices=["cuboid", "kinect", "lidar", "batched", "proposal"])
+    ap.add_argument("--workload", default="kinect", choices=["cuboid", "kinect", "lidar", "batched", "proposal", "mc"])
+    ap.add_argument("--runs", type=int, default=1000, help="independent single-particle runs of the mc workload")
     ap.add_argument("--pairs", type=int, default=64, help="pairs of the batched and proposal workloads")
     ap.add_argument("--workers", type=int, default=16,
                     help="host processes generating the proposal workload's pairs (1: in process)")
@@ -136,6 +137,8 @@ def main():
         return run_batched(args)
     if args.workload == "proposal":
         return run_proposal(args)
+    if args.workload == "mc":
+        return run_mc(args)
 
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 4
@@ -352,7 +355,6 @@ def run_batched(args):
         "batched_equals_sequential_bitwise": same,
         "stage_ms_per_iter": {k: round(v / T, 5) for k, v in stage.items()},
         "init_ms": round(init_ms, 2),
-        "normals_ms": None if normals_ms is None else round(normals_ms, 3),
         "nn_tiling": tiling,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
@@ -363,6 +365,150 @@ def run_batched(args):
         s_.close()
     batch.close()
     print(json.dumps(out), flush=True)
+
+
+def run_mc(args):
+    """The paper's Monte-Carlo ground truth (Sec. V-A) on the Kinect pair:
+    ``runs`` independent single-particle runs (K = 1: SGD-ICP with Adam),
+    starts uniform in +-1 m and +-0.1745 rad, each with its own minibatches,
+    advanced together by one batch context whose pairs share the clouds; then
+    the Stein-ICP posterior (K = 100) on the same pair, timed the same way and
+    scored against the runs (KL of normal fits, per-coordinate OVL), beside
+    the score of 100 of the runs drawn at random and of one half of the runs
+    against the other (the sampling floor)."""
+    import torch
+    import synth
+    from paper_2106_03287_amd import stein_icp as S
+
+    prob = synth.make_problem("kinect", 0)
+    T = args.iters or prob.T
+    R = args.runs
+    nn = "bf16" if args.nn == "auto" else args.nn
+    nn_mode = S.NN_BF16_RERANK if nn == "bf16" else S.NN_FP32
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    src, ref = dev(prob.pair.src), dev(prob.pair.ref)
+    cfg = S.stein_icp_default_config(num_particles=1, batch_size=prob.m, schedule_rows=T, lr=prob.lr,
+                                     seed=synth.MC_SEED, init_half_trans=synth.MC_HALF_TRANS,
+                                     init_half_rot=synth.MC_HALF_ROT, nn_mode=nn_mode,
+                                     autotune=0 if args.tiling else 1)
+    t_init = time.perf_counter()
+    mc = S.SteinICP.batch(cfg, [src] * R, [ref] * R)      # library-drawn starts and minibatches
+    init_ms = (time.perf_counter() - t_init) * 1e3
+    if args.tiling:
+        mc.set_tiling(*[int(x) for x in args.tiling.split(",")])
+    th0 = mc.particles().clone()
+    zeros = torch.zeros_like(th0)
+    scfg = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m, schedule_rows=prob.schedule.shape[0],
+                                      lr=prob.lr, nn_mode=nn_mode)
+    stein = S.SteinICP(scfg, src, ref, dev(prob.theta0), dev(prob.schedule))
+    if nn == "bf16":
+        stein.set_tiling(*[int(x) for x in PINNED_TILING[("kinect", "bf16")].split(",")])
+    sz = torch.zeros_like(dev(prob.theta0))
+
+    def solve_mc():
+        S.stein_icp_set_state(mc.ctx, th0, zeros, zeros, 0)
+        mc.step(T)
+
+    def solve_stein():
+        S.stein_icp_set_state(stein.ctx, dev(prob.theta0), sz, sz, 0)
+        stein.step(T)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    ms_mc = timed(solve_mc, args.steps, args.warmup)
+    ms_stein = timed(solve_stein, args.steps, args.warmup)
+    solve_mc()
+    solve_stein()
+    gt = mc.particles().cpu().numpy()[:, 0]
+    post = stein.particles().cpu().numpy()[0]
+    kl, ovl = S.stein_icp_posterior_scores(post, gt)
+    rng = np.random.default_rng(0)
+    sub = gt[rng.choice(R, min(prob.K, R), replace=False)]
+    kl_sub, ovl_sub = S.stein_icp_posterior_scores(sub, gt)
+    half = rng.permutation(R)
+    kl_half, ovl_half = S.stein_icp_posterior_scores(gt[half[: R // 2]], gt[half[R // 2:]])
+    S.stein_icp_set_state(mc.ctx, th0, zeros, zeros, 0)
+    stage = mc.stage_times(T)
+    nn_ms = mc.time_nn(50)
+    tiling = mc.tiling()
+    M = len(prob.pair.ref)
+    pairs_per_launch = R * prob.m * M
+    if nn == "bf16":
+        mfma = pairs_per_launch * 64 / (nn_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "achieved": round(mfma, 3), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(mfma / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None, "kernel": "nn_bf16_kernel",
+                    "avg_launch_ms": round(nn_ms, 5), "pair_evals_per_launch": pairs_per_launch}
+    else:
+        achieved = pairs_per_launch * FLOPS_PER_PAIR / (nn_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None, "kernel": "nn_fp32_kernel",
+                    "avg_launch_ms": round(nn_ms, 5), "pair_evals_per_launch": pairs_per_launch}
+    r4 = lambda v: [round(float(x), 4) for x in v]  # noqa: E731
+    out = {
+        "metric": METRIC,
+        "value": round(R * T / (ms_mc / 1e3), 2),
+        "unit": "run-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_mc, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16+f32" if nn == "bf16" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "mc", "pair": "kinect", "runs": R, "K": 1, "m": prob.m, "T": T, "M": M,
+                   "start_box": [synth.MC_HALF_TRANS, synth.MC_HALF_ROT], "nn": nn,
+                   "step": "all runs advanced T iterations together (one batch context, shared clouds)"},
+        "stein_ms_per_solve": round(ms_stein, 4),
+        "stein_K": prob.K,
+        "mc_over_stein_time": round(ms_mc / ms_stein, 2),
+        "scores_stein_vs_mc": {"kl_trans": round(float(kl[0]), 4), "kl_rot": round(float(kl[1]), 4), "ovl": r4(ovl)},
+        "scores_100_random_runs_vs_mc": {"kl_trans": round(float(kl_sub[0]), 4), "kl_rot": round(float(kl_sub[1]), 4),
+                                         "ovl": r4(ovl_sub)},
+        "scores_half_vs_half": {"kl_trans": round(float(kl_half[0]), 4), "kl_rot": round(float(kl_half[1]), 4),
+                                "ovl": r4(ovl_half)},
+        "stage_ms_per_iter": {k: round(v / T, 5) for k, v in stage.items()},
+        "init_ms": round(init_ms, 2),
+        "nn_tiling": tiling,
+        "torch": torch.__version__,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_mc(prob, T)
+    mc.close()
+    stein.close()
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_mc(prob, T, budget_s=15.0):
+    """The FP64 oracle's single-particle runs on this host's cores: as many
+    iterations of one run as fit in about ``budget_s`` seconds."""
+    import oracle
+    import synth
+    theta0 = synth.init_particles(synth.MC_SEED, 1, synth.MC_HALF_TRANS, synth.MC_HALF_ROT)
+    sched = synth.minibatch_schedule(synth.MC_SEED, len(prob.pair.src), prob.m, T)
+    cfg = oracle.make_config(1, prob.m, len(prob.pair.src), len(prob.pair.ref), lr=prob.lr)
+    st = oracle.State(theta0)
+    t0 = time.perf_counter()
+    oracle.run(cfg, prob.pair.src, prob.pair.ref, sched, 1, st)
+    per = time.perf_counter() - t0
+    n = int(max(1, min(T - 1, budget_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.run(cfg, prob.pair.src, prob.pair.ref, sched, n, st)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": (n + 1) / (dt + per), "unit": "run-iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"iterations 1-{n + 1} of one single-particle run on the kinect pair (m={prob.m}, "
+                      f"M={len(prob.pair.ref)}), FP64 oracle with OpenMP NN"}
 
 
 # multiply-accumulates of one forward pass per pair: the per-point MLP on

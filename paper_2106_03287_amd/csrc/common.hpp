@@ -27,6 +27,7 @@ struct PairDesc {
     int64_t q_off;      // into the float4 query buffer
     int64_t nq;         // queries of this pair (K * m in a solver context)
     int64_t apack_off;  // into the BF16 reference fragments (64 per 16 references)
+    int64_t part_stride;  // distance between a query's chunk keys (queries of its NN group)
     float c0[4];        // reference centroid (centres the BF16 screen)
     int32_t chunks;     // reference chunks, one partial argmin each
     int32_t chunk;      // references per chunk (multiple of 4 * kTile)
@@ -34,7 +35,9 @@ struct PairDesc {
     int32_t pad_;
 };
 
-// Work item of the NN kernel: pair, query block, reference chunk.
+// Work item of the NN kernel: NN group, query block, reference chunk. An NN
+// group is a run of consecutive pairs on one packed reference (often a
+// single pair); the search treats its queries as one set.
 struct WorkItem {
     int32_t pair, qblock, chunk, pad_;
 };

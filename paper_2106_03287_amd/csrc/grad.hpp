@@ -54,7 +54,7 @@ __device__ __forceinline__ void grad_group(const GradArgs& a, int64_t pk, int64_
         const Pose* __restrict__ P = a.pose + pk;
         for (int i = lt; i < a.m; i += kGradThreads) {
             const int64_t qi = k * a.m + i;
-            const uint64_t key = min_chunk_keys(a.partial + pd.part_off + qi, pd.chunks, nq);
+            const uint64_t key = min_chunk_keys(a.partial + pd.part_off + qi, pd.chunks, pd.part_stride);
             const int32_t j = resolve_key(key, a.queries[pd.q_off + qi], a.ref4 + pd.ref_off, pd.n_ref_pad);
             a.match[p * nq + qi] = j;
             const float4 s = a.src4[pd.src_off + a.sched[pd.sched_off + row * a.m + i]];

@@ -21,9 +21,9 @@ namespace sicp {
 
 struct NNArgs {
     const WorkItem* work;
-    const PairDesc* pairs;
+    const PairDesc* pairs;    // NN groups: queries at q_off, nq of them, keys at part_off
     const float4* ref4;
-    const float4* queries;    // FP32 queries, pair p at pairs[p].q_off, pairs[p].nq of them
+    const float4* queries;
     uint64_t* partial;
     int64_t nwork;
 };

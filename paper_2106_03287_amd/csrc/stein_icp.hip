@@ -161,6 +161,8 @@ struct stein_icp_ctx {
 
     char* arena = nullptr;
     PairDesc* d_pairs = nullptr;
+    std::vector<PairDesc> groups;   // NN groups (runs of consecutive pairs on one packed reference)
+    PairDesc* d_groups = nullptr;
     float4* src4 = nullptr;
     float4* ref4 = nullptr;
     int32_t* sched = nullptr;
@@ -299,33 +301,58 @@ hipError_t launch_nn(const Tiling& t, unsigned nwork, NNArgs a, hipStream_t s)
     return hipGetLastError();
 }
 
+// NN groups and the work table. Consecutive pairs on the same packed
+// reference with the same chunking form one group: their queries are
+// contiguous, so the search runs them as one query set (full query blocks
+// where each pair alone would leave a ragged one). A group's chunk keys are
+// chunk-major over all its queries; pair l of the group finds its keys at
+// part_off + l K m with stride part_stride.
 void build_work(stein_icp_ctx* c)
 {
     c->work.clear();
-    int64_t part = 0;
+    c->groups.clear();
     for (int32_t p = 0; p < c->P; ++p) {
         PairDesc& pd = c->pairs[p];
         pd.chunk = c->tiling.chunk[p];
         pd.chunks = (int32_t)ceil_div(pd.n_ref_pad, pd.chunk);
-        pd.qblocks = (int32_t)ceil_div(c->nq, (int64_t)kWave * c->tiling.q);
-        pd.part_off = part;
-        part += (int64_t)pd.chunks * c->nq;
     }
-    // chunk-major order inside a pair so neighbouring workgroups (which the
+    int64_t part = 0;
+    for (int32_t p0 = 0; p0 < c->P;) {
+        int32_t p1 = p0 + 1;
+        while (p1 < c->P && c->pairs[p1].ref_off == c->pairs[p0].ref_off &&
+               c->pairs[p1].n_ref_pad == c->pairs[p0].n_ref_pad && c->pairs[p1].chunk == c->pairs[p0].chunk)
+            ++p1;
+        PairDesc g = c->pairs[p0];
+        g.nq = (int64_t)(p1 - p0) * c->nq;
+        g.q_off = c->pairs[p0].q_off;
+        g.qblocks = (int32_t)ceil_div(g.nq, (int64_t)kWave * c->tiling.q);
+        g.part_off = part;
+        g.part_stride = g.nq;
+        for (int32_t p = p0; p < p1; ++p) {
+            PairDesc& pd = c->pairs[p];
+            pd.part_off = part + (int64_t)(p - p0) * c->nq;
+            pd.part_stride = g.nq;
+            pd.qblocks = g.qblocks;
+        }
+        part += (int64_t)g.chunks * g.nq;
+        c->groups.push_back(g);
+        p0 = p1;
+    }
+    // chunk-major order inside a group so neighbouring workgroups (which the
     // dispatcher spreads round-robin over the eight XCDs) read different
     // chunks of the same queries; every reference array here fits each
     // XCD's L2, so locality across XCDs is not the limiter.
-    for (int32_t p = 0; p < c->P; ++p) {
-        const PairDesc& pd = c->pairs[p];
-        for (int32_t b = 0; b < pd.qblocks; ++b)
-            for (int32_t ch = 0; ch < pd.chunks; ++ch) c->work.push_back(WorkItem{p, b, ch, 0});
+    for (int32_t gi = 0; gi < (int32_t)c->groups.size(); ++gi) {
+        const PairDesc& g = c->groups[gi];
+        for (int32_t b = 0; b < g.qblocks; ++b)
+            for (int32_t ch = 0; ch < g.chunks; ++ch) c->work.push_back(WorkItem{gi, b, ch, 0});
     }
 }
 
 int64_t partial_elems(const stein_icp_ctx* c)
 {
     int64_t n = 0;
-    for (const auto& pd : c->pairs) n += (int64_t)pd.chunks * c->nq;
+    for (const auto& g : c->groups) n += (int64_t)g.chunks * g.nq;
     return n;
 }
 
@@ -342,6 +369,8 @@ int upload_tiling(stein_icp_ctx* c, hipStream_t s)
         return fail(STEIN_ICP_E_NOMEM, "device allocation of the NN work table failed");
     }
     HIP_TRY(hipMemcpyAsync(c->d_pairs, c->pairs.data(), sizeof(PairDesc) * c->P, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c->d_groups, c->groups.data(), sizeof(PairDesc) * c->groups.size(),
+                           hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(c->d_work, c->work.data(), sizeof(WorkItem) * c->work.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
@@ -353,7 +382,7 @@ NNArgs nn_args(const stein_icp_ctx* c)
 {
     NNArgs a{};
     a.work = c->d_work;
-    a.pairs = c->d_pairs;
+    a.pairs = c->d_groups;
     a.ref4 = c->ref4;
     a.queries = c->queries;
     a.partial = c->partial;
@@ -401,7 +430,7 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
         if (c->cfg.nn_mode == STEIN_ICP_NN_BF16_RERANK) {
             NNBf16Args b{};
             b.work = c->d_work;
-            b.pairs = c->d_pairs;
+            b.pairs = c->d_groups;
             b.ref4 = c->ref4;
             b.apack = c->apack;
             b.queries = c->queries;
@@ -790,6 +819,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     };
     const size_t o_pairs = take(sizeof(PairDesc) * P);
     const size_t o_upairs = take(sizeof(PairDesc) * P);   // the pairs that own their reference
+    const size_t o_groups = take(sizeof(PairDesc) * P);
     const size_t o_src = take(sizeof(float4) * so);
     const size_t o_ref = take(sizeof(float4) * ro);
     const size_t o_sched = take(sizeof(int32_t) * (size_t)P * rows * m);
@@ -811,6 +841,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
         return fail(STEIN_ICP_E_NOMEM, "device allocation of " + std::to_string(off) + " bytes failed");
     }
     c->d_pairs = (PairDesc*)(c->arena + o_pairs);
+    c->d_groups = (PairDesc*)(c->arena + o_groups);
     c->src4 = (float4*)(c->arena + o_src);
     c->ref4 = (float4*)(c->arena + o_ref);
     c->sched = (int32_t*)(c->arena + o_sched);
@@ -1156,6 +1187,7 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     PairDesc pd{};
     pd.q_off = 0;
     pd.nq = nq;
+    pd.part_stride = nq;
     pd.n_ref = n_ref;
     pd.n_ref_pad = round_up(n_ref, kTile);
     const bool bf16 = mode == STEIN_ICP_NN_BF16_RERANK;
