@@ -186,7 +186,7 @@ int stein_icp_nn_tiling(const stein_icp_ctx *ctx, int32_t *queries_per_lane, int
                         int32_t *chunk, int32_t *chunks, int32_t *persist, double *tuned_ms);
 
 /* Force the nearest-neighbour work shape: queries_per_lane in {1, 2, 4},
- * waves in {4, 8, 16}, chunk a positive multiple of 16 references (capped
+ * waves in {4, 8, 16}, chunk a positive multiple of 32 references (capped
  * at each pair's padded reference count), persist in [0, 64] as above. The
  * shape changes only how the search is split over workgroups, never its
  * result. Blocking (reallocates the per-chunk key buffer and synchronises

@@ -7,7 +7,8 @@
 namespace sicp {
 
 constexpr int kWave = 64;            // CDNA wavefront width
-constexpr int kTile = 16;            // references per tile of the NN scan
+constexpr int kTile = 16;            // references per tile of the NN scan (and of a key's tile index)
+constexpr int kRefPad = 32;          // references are padded to a multiple of this (the BF16 screen's block)
 constexpr float kPadCoord = 1e18f;   // coordinate of padding references
 constexpr int kMaxK = 1024;          // particles per pair (one workgroup)
 constexpr int kSvgdThreads = 1024;   // threads of the per-pair SVGD workgroup
@@ -20,13 +21,13 @@ struct PairDesc {
     int64_t ref_off;    // into ref4
     int64_t n_src;
     int64_t n_ref;      // real references
-    int64_t n_ref_pad;  // padded to a multiple of kTile with far-away points
+    int64_t n_ref_pad;  // padded to a multiple of kRefPad with far-away points
     int64_t sched_off;  // into the int32 schedule (rows x m)
     int64_t part_off;   // into the uint64 partial-argmin buffer (chunks x K*m)
     int64_t n_scale;    // N in "N gbar"
     int64_t q_off;      // into the float4 query buffer
     int64_t nq;         // queries of this pair (K * m in a solver context)
-    int64_t apack_off;  // into the BF16 reference fragments (64 per 16 references)
+    int64_t apack_off;  // into the BF16 reference fragments (4 uint4 per reference)
     int64_t part_stride;  // distance between a query's chunk keys (queries of its NN group)
     float c0[4];        // reference centroid (centres the BF16 screen)
     int32_t chunks;     // reference chunks, one partial argmin each

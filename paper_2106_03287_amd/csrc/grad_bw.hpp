@@ -21,11 +21,14 @@ inline size_t grad_bw_lds_bytes(int K)
     return bw > gr ? bw : gr;
 }
 
-// grid: 2 P + ceil(P K / kGradGroups) workgroups of kSvgdThreads threads.
-__global__ __launch_bounds__(kSvgdThreads) void grad_bandwidth_kernel(GradArgs g, SvgdArgs v, int32_t n_pairs)
+// grid: 2 bw_pairs + ceil(P K / kGradGroups) workgroups of kSvgdThreads
+// threads. bw_pairs is P, or 0 when the bandwidths are constants (a fixed
+// bandwidth, or K = 1) written once at init.
+__global__ __launch_bounds__(kSvgdThreads) void grad_bandwidth_kernel(GradArgs g, SvgdArgs v, int32_t n_pairs,
+                                                                      int32_t bw_pairs)
 {
     extern __shared__ double lds[];
-    const int64_t bw_blocks = 2 * (int64_t)n_pairs;
+    const int64_t bw_blocks = 2 * (int64_t)bw_pairs;
     if ((int64_t)blockIdx.x < bw_blocks) {   // whole workgroup
         SelectShared& sh = *reinterpret_cast<SelectShared*>(lds);
         double* dyn = lds + (sizeof(SelectShared) + 15) / 16 * 2;

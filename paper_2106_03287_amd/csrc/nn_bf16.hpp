@@ -2,34 +2,39 @@
 // rerank.
 //
 // Screen: squared distances in the expanded form |q|^2 + |r|^2 - 2 q.r on
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation. Both sides are centred on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation. Both sides are centred on
 // the pair's reference centroid c0, and every FP32 value is split into three
 // BF16 parts (x = h + m + l, the usual BF16x3 decomposition), so each product
-// keeps about 24 bits; 24 of the 32 K slots are used:
+// keeps about 24 bits; 24 of 32 K slots are used, over two products of
+// K = 16 accumulated in FP32:
 //    k  0- 2: r_h  * -2 q_h      k  9-11: r_h * -2 q_l      k 18-20: |r|^2 (h, m, l) * 1
 //    k  3- 5: r_h  * -2 q_m      k 12-14: r_l * -2 q_h      k 21-23: 1 * |q|^2 (h, m, l)
 //    k  6- 8: r_m  * -2 q_h      k 15-17: r_m * -2 q_m      k 24-31: 0
-// The references are the A operand (16 per block, pre-packed in the lane
-// layout at init), the queries the B operand (16 per group, built once per
-// wavefront). Lane l owns query l % 16 of each group and receives rows
-// 4 (l / 16) .. +3 of each 16-reference block; it keeps only the minimum of
-// those four values and the block where it fell.
+// The references are the A operand (32 per block, pre-packed in the lane
+// layout at init), the queries the B operand (32 per group, built once per
+// wavefront). Lane l owns query l % 32 of each group and receives rows
+// 8 i + 4 (l / 32) + 0..3 (i = 0..3) of each 32-reference block; it keeps
+// only the minimum of those sixteen values and the block where it fell. The
+// wide product gives each lane sixteen values to reduce per pair of matrix
+// instructions (three-input minimums), where a 16 x 16 product gives four
+// per instruction: the vector-ALU work per distance, which bounds the screen,
+// about halves.
 //
 // Rerank: each lane recomputes the exact FP32 distance (the same operation
-// sequence as the FP32 search) of its four references in its best block; the
-// four lanes of a query merge their (distance, tile) keys. The key format is
-// the FP32 search's, so chunk reduction and tile resolution downstream are
-// shared.
+// sequence as the FP32 search) of its sixteen references in its best block,
+// keyed by their 16-reference tile; the two lanes of a query merge their
+// (distance, tile) keys. The key format is the FP32 search's, so chunk
+// reduction and tile resolution downstream are shared.
 //
 // Certificate: the result is the FP32 search's exact chunk minimum, ties
 // included. Let S be the screened and F the FP32 distance of a reference.
 // |S - F| <= eps = 28 u (|q_c| + R)^2 + 6.2 u F (u = 2^-24, R the pair's
-// largest centred reference norm): 23 FP32 additions of 24 exact BF16
-// products whose magnitudes sum to at most (|q_c| + |r_c|)^2, the dropped
-// BF16 cross terms and the FP32 norms, the FP32 centring, and the FP32
-// direct difference. Each lane also keeps s2, the smallest block minimum of
-// its rows outside its best block. After the workgroup merges its keys into
-// the chunk minimum F_wg, a lane whose references outside its best block all
+// largest centred reference norm): FP32 additions of 24 exact BF16 products
+// whose magnitudes sum to at most (|q_c| + |r_c|)^2, the dropped BF16 cross
+// terms and the FP32 norms, the FP32 centring, and the FP32 direct
+// difference. Each lane also keeps s2, the smallest block minimum of its
+// rows outside its best block. After the workgroup merges its keys into the
+// chunk minimum F_wg, a lane whose references outside its best block all
 // satisfy F > F_wg -- guaranteed when s2 - 32 u (|q_c| + R)^2 > F_wg (1 + 8 u)
 // -- has lost nothing; otherwise that lane's own rows of its wavefront's
 // blocks are searched again in FP32 by the wavefront and folded into the
@@ -43,6 +48,7 @@ namespace sicp {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
 
 // Round to nearest even BF16 (finite inputs), returned as bits.
@@ -107,16 +113,23 @@ __device__ __forceinline__ u16x8_t slot_fragment(const float c[3], bool ref, int
     return v;
 }
 
-// grid (blocks of 16 references, pairs) x 64 lanes: A fragments of the
-// centred references, 16 bytes per lane and block.
+constexpr int kBlk = kRefPad;   // references per block of the screen (the A operand's 32 rows)
+
+// Row of the 32-reference block held by output t (0..15) of a lane in half h
+// (lane / 32) of the 32 x 32 product.
+__device__ __forceinline__ int blk_row(int t, int h) { return 8 * (t >> 2) + 4 * h + (t & 3); }
+
+// grid (blocks of 32 references / 4, groups) x 256 threads, one wavefront
+// per block: each lane's two A fragments (K slots 8 h .. 8 h + 7 and
+// 16 + 8 h .. +7 of row lane % 32), 32 bytes per lane and block.
 __global__ void pack_bf16_refs_kernel(const PairDesc* __restrict__ pairs, const float4* __restrict__ ref4,
                                       uint4* __restrict__ apack)
 {
     const PairDesc pd = pairs[blockIdx.y];
     const int64_t blk = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & (kWave - 1);
-    if (blk >= pd.n_ref_pad / kTile) return;
-    const float4 r = ref4[pd.ref_off + blk * kTile + (lane & 15)];
+    if (blk >= pd.n_ref_pad / kBlk) return;
+    const float4 r = ref4[pd.ref_off + blk * kBlk + (lane & 31)];
     float c[3];
     {
 #pragma clang fp contract(off)
@@ -124,28 +137,29 @@ __global__ void pack_bf16_refs_kernel(const PairDesc* __restrict__ pairs, const 
         c[1] = r.y - pd.c0[1];
         c[2] = r.z - pd.c0[2];
     }
-    const u16x8_t v = slot_fragment(c, true, lane >> 4);
-    apack[pd.apack_off + blk * kWave + lane] = __builtin_bit_cast(uint4, v);
+    uint4* out = apack + pd.apack_off + (blk * kWave + lane) * 2;
+    out[0] = __builtin_bit_cast(uint4, slot_fragment(c, true, lane >> 5));
+    out[1] = __builtin_bit_cast(uint4, slot_fragment(c, true, 2 + (lane >> 5)));
 }
 
 
-// A work item holds 64 Q queries (as in the FP32 search), taken as 4 Q groups
-// of 16 by every wavefront of the workgroup.
+// A work item holds 64 Q queries (as in the FP32 search), taken as 2 Q groups
+// of 32 by every wavefront of the workgroup.
 template <int Q, int W>
 __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem w, uint64_t (*sk)[kWave * Q])
 {
-    constexpr int G = 4 * Q;   // query groups of 16
+    constexpr int G = 2 * Q;   // query groups of 32
     const PairDesc pd = a.pairs[w.pair];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x >> 6);
     const int64_t nq = pd.nq;
     const int64_t qbase = (int64_t)w.qblock * kWave * Q;
-    const int j = lane & 15, s = lane >> 4;
+    const int j = lane & 31, h = lane >> 5;
 
-    bf16x8_t bfrag[G];
+    bf16x8_t b0[G], b1[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int64_t qi = qbase + 16 * g + j;
+        const int64_t qi = qbase + 32 * g + j;
         const float4 qf = qi < nq ? a.queries[pd.q_off + qi] : make_float4(0.f, 0.f, 0.f, 0.f);
         float c[3];
         {
@@ -154,15 +168,16 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
             c[1] = qf.y - pd.c0[1];
             c[2] = qf.z - pd.c0[2];
         }
-        bfrag[g] = __builtin_bit_cast(bf16x8_t, slot_fragment(c, false, s));
+        b0[g] = __builtin_bit_cast(bf16x8_t, slot_fragment(c, false, h));
+        b1[g] = __builtin_bit_cast(bf16x8_t, slot_fragment(c, false, 2 + h));
     }
 
     const int64_t c0 = (int64_t)w.chunk * pd.chunk;
     const int64_t cend = min(c0 + (int64_t)pd.chunk, pd.n_ref_pad);
-    const int64_t ntiles = (cend - c0) / kTile;
-    const int64_t t0 = (ntiles * wave) / W;
-    const int64_t t1 = (ntiles * (wave + 1)) / W;
-    const uint4* __restrict__ ap = a.apack + pd.apack_off + (c0 / kTile) * kWave + lane;
+    const int64_t nblk = (cend - c0) / kBlk;
+    const int64_t t0 = (nblk * wave) / W;
+    const int64_t t1 = (nblk * (wave + 1)) / W;
+    const uint4* __restrict__ ap = a.apack + pd.apack_off + ((c0 / kBlk) * kWave + lane) * 2;
 
     float best[G], sec[G];   // best block minimum, and the smallest of the other blocks
     int32_t bblk[G];
@@ -172,21 +187,38 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
         sec[g] = __builtin_inff();
         bblk[g] = (int32_t)t0;
     }
-    uint4 anext = t0 < t1 ? ap[t0 * kWave] : make_uint4(0u, 0u, 0u, 0u);
+    uint4 an0 = make_uint4(0u, 0u, 0u, 0u), an1 = an0;
+    if (t0 < t1) {
+        an0 = ap[t0 * 2 * kWave];
+        an1 = ap[t0 * 2 * kWave + 1];
+    }
     for (int64_t tt = t0; tt < t1; ++tt) {
-        const bf16x8_t afrag = __builtin_bit_cast(bf16x8_t, anext);
-        if (tt + 1 < t1) anext = ap[(tt + 1) * kWave];   // next block's fragment in flight
-        // all groups' products first (independent accumulators keep the
-        // matrix pipeline busy), then the minimum epilogues
-        f32x4_t acc[G];
+        const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, an0);
+        const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, an1);
+        if (tt + 1 < t1) {   // next block's fragments in flight
+            an0 = ap[(tt + 1) * 2 * kWave];
+            an1 = ap[(tt + 1) * 2 * kWave + 1];
+        }
+        // all groups' first products, then their second ones (independent
+        // accumulators keep the matrix pipeline busy), then the minimum
+        // epilogues
+        f32x16_t acc[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const f32x4_t zero = {0.f, 0.f, 0.f, 0.f};
-            acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[g], zero, 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < 16; ++t) acc[g][t] = 0.f;
+            acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0[g], acc[g], 0, 0, 0);
         }
 #pragma unroll
+        for (int g = 0; g < G; ++g) acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1[g], acc[g], 0, 0, 0);
+#pragma unroll
         for (int g = 0; g < G; ++g) {
-            const float mn = __builtin_fminf(__builtin_fminf(acc[g][0], acc[g][1]), __builtin_fminf(acc[g][2], acc[g][3]));
+            float m4[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                m4[i] = __builtin_fminf(__builtin_fminf(acc[g][4 * i], acc[g][4 * i + 1]),
+                                        __builtin_fminf(acc[g][4 * i + 2], acc[g][4 * i + 3]));
+            const float mn = __builtin_fminf(__builtin_fminf(m4[0], m4[1]), __builtin_fminf(m4[2], m4[3]));
             sec[g] = __builtin_fminf(sec[g], __builtin_fmaxf(best[g], mn));
             const bool better = mn < best[g];
             best[g] = better ? mn : best[g];
@@ -194,32 +226,35 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
         }
     }
 
-    // exact FP32 rerank of the lane's four references in its best block,
-    // then the minimum over the four lanes of each query
+    // exact FP32 rerank of the lane's sixteen references in its best block
+    // (keyed by their 16-reference tile), then the minimum over the two
+    // lanes of each query
     const float4* __restrict__ rp = a.ref4 + pd.ref_off + c0;
     uint64_t key[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int64_t qi = qbase + 16 * g + j;
+        const int64_t qi = qbase + 32 * g + j;
         const float4 qf = qi < nq ? a.queries[pd.q_off + qi] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float4* __restrict__ r = rp + (int64_t)bblk[g] * kTile + 4 * s;
-        float bd = __builtin_inff();
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const float4 rr = r[u];
-            bd = __builtin_fminf(bd, dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z));
+        const int64_t rb = (int64_t)bblk[g] * kBlk;
+        uint64_t k = ~0ull;
+        if (t0 < t1) {
+#pragma unroll 4
+            for (int t = 0; t < 16; ++t) {
+                const int row = blk_row(t, h);
+                const float4 rr = rp[rb + row];
+                k = min(k, pack_key(dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z),
+                                    (uint32_t)((c0 + rb + row) / kTile)));
+            }
         }
-        uint64_t k = (t0 < t1) ? pack_key(bd, (uint32_t)(c0 / kTile + bblk[g])) : ~0ull;
-        k = min(k, (uint64_t)__shfl_xor((unsigned long long)k, 16));
         k = min(k, (uint64_t)__shfl_xor((unsigned long long)k, 32));
         key[g] = k;
     }
 
-    // lanes 0..15 hold the merged keys of the G groups; merge the W waves
+    // lanes 0..31 hold the merged keys of the G groups; merge the W waves
     // into the chunk minimum of each query (kept in sk[0])
 #pragma unroll
     for (int g = 0; g < G; ++g)
-        if (s == 0) sk[wave][16 * g + j] = key[g];
+        if (h == 0) sk[wave][32 * g + j] = key[g];
     __syncthreads();
     for (int jj = threadIdx.x; jj < kWave * Q; jj += kWave * W) {
         uint64_t k0 = sk[0][jj];
@@ -229,17 +264,17 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     }
     __syncthreads();
     // certificate of every lane against the chunk minimum; a lane that fails
-    // has its own rows of its own blocks (4 (t1 - t0) references) searched
+    // has its own rows of its own blocks (16 (t1 - t0) references) searched
     // again in FP32 by its wavefront, folded into the chunk minimum in LDS
     if (t0 < t1) {
         constexpr double u = 0x1.0p-24;
-        const int64_t nref = 4 * (t1 - t0);
+        const int64_t nref = 16 * (t1 - t0);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const int64_t qi = qbase + 16 * g + j;
+            const int64_t qi = qbase + 32 * g + j;
             bool fail = false;
             if (qi < nq) {
-                const float fwg = __uint_as_float((uint32_t)(sk[0][16 * g + j] >> 32));
+                const float fwg = __uint_as_float((uint32_t)(sk[0][32 * g + j] >> 32));
                 const float4 qf = a.queries[pd.q_off + qi];
                 float c[3];
                 {
@@ -257,17 +292,17 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
             while (mask != 0ull) {   // wave-uniform
                 const int b = __ffsll((long long)mask) - 1;
                 mask &= mask - 1ull;
-                const int fj = b & 15, fs = b >> 4;
-                const float4 qf = a.queries[pd.q_off + qbase + 16 * g + fj];
+                const int fj = b & 31, fh = b >> 5;
+                const float4 qf = a.queries[pd.q_off + qbase + 32 * g + fj];
                 uint64_t kb = ~0ull;
                 for (int64_t e = lane; e < nref; e += kWave) {
-                    const int64_t r = c0 + (t0 + e / 4) * kTile + 4 * fs + (e & 3);
+                    const int64_t r = c0 + (t0 + e / 16) * kBlk + blk_row((int)(e & 15), fh);
                     const float4 rr = a.ref4[pd.ref_off + r];
                     kb = min(kb, pack_key(dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z), (uint32_t)(r / kTile)));
                 }
 #pragma unroll
                 for (int o = kWave / 2; o > 0; o >>= 1) kb = min(kb, (uint64_t)__shfl_xor((unsigned long long)kb, o));
-                if (lane == 0) atomicMin((unsigned long long*)&sk[0][16 * g + fj], (unsigned long long)kb);
+                if (lane == 0) atomicMin((unsigned long long*)&sk[0][32 * g + fj], (unsigned long long)kb);
             }
         }
     }

@@ -190,6 +190,13 @@ struct stein_icp_ctx {
 
 namespace {
 
+// The bandwidths do not depend on the particles: a fixed bandwidth, or one
+// particle (h = 1 then, as the median heuristic's guard gives).
+bool const_bandwidth(const stein_icp_config& c)
+{
+    return c.bandwidth_mode == STEIN_ICP_BW_FIXED || c.num_particles < 2;
+}
+
 SvgdParams svgd_params(const stein_icp_config& c)
 {
     SvgdParams p{};
@@ -455,13 +462,14 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
     g.K = c->K;
     g.m = c->m;
     g.rows = c->rows;
-    const int64_t blocks = 2 * (int64_t)c->P + ceil_div((int64_t)c->P * c->K, kGradGroups);
+    const int32_t bw_pairs = const_bandwidth(c->cfg) ? 0 : c->P;
+    const int64_t blocks = 2 * (int64_t)bw_pairs + ceil_div((int64_t)c->P * c->K, kGradGroups);
     hipLaunchKernelGGL(grad_bandwidth_kernel, dim3((unsigned)blocks), dim3(kSvgdThreads), grad_bw_lds_bytes(c->K), s,
-                       g, svgd_args(c), c->P);
+                       g, svgd_args(c), c->P, bw_pairs);
     return hipGetLastError();
     }
     const SvgdArgs v = svgd_args(c);
-    hipLaunchKernelGGL(svgd_phi_update_kernel, dim3((unsigned)ceil_div(c->K, 4), (unsigned)c->P), dim3(256), 0, s, v);
+    hipLaunchKernelGGL(svgd_phi_update_kernel, dim3((unsigned)c->K, (unsigned)c->P), dim3(kPhiThreads), 0, s, v);
     return hipGetLastError();
 }
 
@@ -768,7 +776,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
         pd.ref_off = own_ref[p] == p ? ro : c->pairs[own_ref[p]].ref_off;
         pd.n_src = n_src[p];
         pd.n_ref = n_ref[p];
-        pd.n_ref_pad = round_up(n_ref[p], kTile);
+        pd.n_ref_pad = round_up(n_ref[p], kRefPad);
         pd.sched_off = (int64_t)p * rows * m;
         pd.n_scale = cfg->n_scale > 0 ? cfg->n_scale : n_src[p];
         pd.q_off = (int64_t)p * nq;
@@ -806,7 +814,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
             }
             bf16_centre(h.data(), pd.n_ref, pd);
             pd.apack_off = apack_n;
-            apack_n += pd.n_ref_pad / kTile * kWave;
+            apack_n += 4 * pd.n_ref_pad;
         }
     }
     const int64_t PK6 = (int64_t)P * K * 6;
@@ -901,6 +909,16 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
         if (hipMemcpyAsync(c->theta, hinit.data(), 8 * hinit.size(), hipMemcpyHostToDevice, s) != hipSuccess)
             return bail(fail(STEIN_ICP_E_DEVICE, "particle upload failed"));
     }
+    std::vector<double> hconst;
+    if (const_bandwidth(*cfg)) {
+        const bool fixed = cfg->bandwidth_mode == STEIN_ICP_BW_FIXED;
+        for (int32_t p = 0; p < P; ++p) {
+            hconst.push_back(fixed ? cfg->fixed_h_trans : 1.0);
+            hconst.push_back(fixed ? cfg->fixed_h_rot : 1.0);
+        }
+        if (hipMemcpyAsync(c->h, hconst.data(), 8 * hconst.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+            return bail(fail(STEIN_ICP_E_DEVICE, "bandwidth upload failed"));
+    }
     hipLaunchKernelGGL(pose_kernel, grid1d((int64_t)P * K, 256), dim3(256), 0, s, c->theta, c->pose, (int64_t)P * K);
     if (hipGetLastError() != hipSuccess) return bail(fail(STEIN_ICP_E_DEVICE, "init kernel launch failed"));
     if (hipMemcpyAsync(c->d_pairs, c->pairs.data(), sizeof(PairDesc) * P, hipMemcpyHostToDevice, s) != hipSuccess)
@@ -911,7 +929,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
         if (own_ref[p] == p) uref.push_back(c->pairs[p]);
     if (bf16) {
         int64_t maxblk = 0;
-        for (const auto& pd : uref) maxblk = std::max<int64_t>(maxblk, pd.n_ref_pad / kTile);
+        for (const auto& pd : uref) maxblk = std::max<int64_t>(maxblk, pd.n_ref_pad / kRefPad);
         PairDesc* d_upairs = (PairDesc*)(c->arena + o_upairs);
         if (hipMemcpyAsync(d_upairs, uref.data(), sizeof(PairDesc) * uref.size(), hipMemcpyHostToDevice, s) !=
                 hipSuccess ||
@@ -1099,12 +1117,13 @@ int stein_icp_set_nn_tiling(stein_icp_ctx* ctx, int32_t qpl, int32_t waves, int3
     if (persist < 0 || persist > 64) return fail(STEIN_ICP_E_INVALID, "persist must be in [0, 64]");
     if (qpl != 1 && qpl != 2 && qpl != 4) return fail(STEIN_ICP_E_INVALID, "queries_per_lane must be 1, 2 or 4");
     if (waves != 4 && waves != 8 && waves != 16) return fail(STEIN_ICP_E_INVALID, "waves must be 4, 8 or 16");
-    if (chunk < kTile || chunk % kTile != 0) return fail(STEIN_ICP_E_INVALID, "chunk must be a positive multiple of 16");
+    if (chunk < kRefPad || chunk % kRefPad != 0)
+        return fail(STEIN_ICP_E_INVALID, "chunk must be a positive multiple of 32");
     Tiling t;
     t.q = qpl;
     t.w = waves;
     t.persist = persist;
-    for (const auto& pd : ctx->pairs) t.chunk.push_back((int32_t)std::min<int64_t>(chunk, round_up(pd.n_ref_pad, kTile)));
+    for (const auto& pd : ctx->pairs) t.chunk.push_back((int32_t)std::min<int64_t>(chunk, pd.n_ref_pad));
     const Tiling old = ctx->tiling;
     ctx->tiling = t;
     const int rc = upload_tiling(ctx, (hipStream_t)hip_stream);
@@ -1189,7 +1208,7 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     pd.nq = nq;
     pd.part_stride = nq;
     pd.n_ref = n_ref;
-    pd.n_ref_pad = round_up(n_ref, kTile);
+    pd.n_ref_pad = round_up(n_ref, kRefPad);
     const bool bf16 = mode == STEIN_ICP_NN_BF16_RERANK;
     if (bf16) {
         std::vector<float> h((size_t)n_ref * 3);
@@ -1216,7 +1235,7 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     const size_t o_q = take(16 * (size_t)nq), o_r = take(16 * (size_t)pd.n_ref_pad);
     const size_t o_p = take(8 * (size_t)pd.chunks * nq), o_w = take(sizeof(WorkItem) * work.size());
     const size_t o_d = take(sizeof(PairDesc)), o_f = take(64);
-    const size_t o_ap = take(bf16 ? sizeof(uint4) * (size_t)(pd.n_ref_pad / kTile * kWave) : 16);
+    const size_t o_ap = take(bf16 ? sizeof(uint4) * (size_t)(4 * pd.n_ref_pad) : 16);
     char* mem = nullptr;
     if (hipMalloc(&mem, off) != hipSuccess) {
         (void)hipGetLastError();
@@ -1246,7 +1265,7 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     if (e == hipSuccess && flag) rc = fail(STEIN_ICP_E_INVALID, "a coordinate is non-finite or above 1e9");
     if (e == hipSuccess && !rc) {
         if (bf16) {
-            e = launch_pack_bf16(a.pairs, 1, pd.n_ref_pad / kTile, a.ref4, (uint4*)(mem + o_ap), s);
+            e = launch_pack_bf16(a.pairs, 1, pd.n_ref_pad / kRefPad, a.ref4, (uint4*)(mem + o_ap), s);
             NNBf16Args b{};
             b.work = a.work;
             b.pairs = a.pairs;

@@ -13,10 +13,10 @@
 //    Larger K keep FP64 distances in global memory and bin by value. A radix
 //    select over IEEE-754 bit patterns covers the degenerate cases. It
 //    depends only on the particles, so it runs beside the gradients.
-//  * svgd_phi_update_kernel, one wavefront per particle k:
+//  * svgd_phi_update_kernel, one 256-thread workgroup per particle k:
 //    phi_k = (1/K) sum_l [G_l k(l,k) + grad_{theta_l} k(l,k)] with
-//    G_l = -N gbar_l + grad log p(theta_l) (Eq. 10 with Eqs. 14-15), lanes over
-//    l and a fixed-shape shuffle reduction; then Adam on -phi (or
+//    G_l = -N gbar_l + grad log p(theta_l) (Eq. 10 with Eqs. 14-15), threads
+//    over l and a fixed-shape reduction; then Adam on -phi (or
 //    theta += lr phi) for particle k, written to the other particle buffer
 //    (other wavefronts still read the current particles; the buffers swap
 //    roles every iteration), the particle's next pose and its FP32 queries
@@ -509,14 +509,23 @@ inline size_t bandwidth_lds_bytes(int K)
     return (b + 15) / 16 * 16;
 }
 
-// grid (ceil(K / 4), pairs), 256 threads: one wavefront per particle.
-__global__ __launch_bounds__(256) void svgd_phi_update_kernel(SvgdArgs a)
+constexpr int kPhiThreads = 256;   // threads per particle of the direction / update kernel
+
+// grid (K, pairs), kPhiThreads threads: one workgroup per particle. Thread t
+// takes the kernel terms of particles l = t, t + 256, ...; the sums are
+// combined by a fixed-shape tree (wavefront shuffles, then the four
+// wavefronts in order), Adam updates the six components, and every thread
+// transforms its minibatch points for the next iteration.
+__global__ __launch_bounds__(kPhiThreads) void svgd_phi_update_kernel(SvgdArgs a)
 {
+    __shared__ double red[kPhiThreads / kWave][6];
+    __shared__ double tn_sh[6];
     const int64_t p = blockIdx.y;
     const int K = a.K;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int k = blockIdx.x * 4 + uniform(threadIdx.x >> 6);
-    if (k >= K) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid >> 6;
+    const int k = blockIdx.x;
     const PairDesc pd = a.pairs[p];
     const double* __restrict__ th = a.theta + p * K * 6;
     const double* __restrict__ gb = a.gbar + p * K * 6;
@@ -528,7 +537,7 @@ __global__ __launch_bounds__(256) void svgd_phi_update_kernel(SvgdArgs a)
     for (int d = 0; d < 6; ++d) tk[d] = th[6 * k + d];
 
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int l = lane; l < K; l += kWave) {
+    for (int l = tid; l < K; l += kPhiThreads) {
         double tl[6], G[6];
 #pragma unroll
         for (int d = 0; d < 6; ++d) tl[d] = th[6 * l + d];
@@ -562,17 +571,26 @@ __global__ __launch_bounds__(256) void svgd_phi_update_kernel(SvgdArgs a)
         for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
         acc[d] = x;
     }
-    // lanes 0..5 update one component each
-    double phi_d = 0.0, tnew = 0.0;
-#pragma unroll
-    for (int d = 0; d < 6; ++d)
-        if (lane == d) phi_d = acc[d] / K;
-    const int64_t e = (p * K + k) * 6 + lane;
     if (lane < 6) {
+        double v = 0.0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d)
+            if (lane == d) v = acc[d];
+        red[wave][lane] = v;
+    }
+    __syncthreads();
+    // threads 0..5 update one component each
+    if (tid < 6) {
 #pragma clang fp contract(off)
+        double sum = red[0][tid];
+#pragma unroll
+        for (int w = 1; w < kPhiThreads / kWave; ++w) sum += red[w][tid];
+        const double phi_d = sum / K;
+        const int64_t e = (p * K + k) * 6 + tid;
+        double tnew;
         a.phi[e] = phi_d;
         if (a.prm.optimizer == 1) {
-            tnew = th[6 * k + lane] + a.prm.lr * phi_d;
+            tnew = th[6 * k + tid] + a.prm.lr * phi_d;
         } else {
             const double t_new = (double)(a.step[p] + 1);
             const double bc1 = 1.0 - pow(a.prm.beta1, t_new);
@@ -584,31 +602,34 @@ __global__ __launch_bounds__(256) void svgd_phi_update_kernel(SvgdArgs a)
             a.vel[e] = vv;
             const double mhat = mm / bc1;
             const double vhat = vv / bc2;
-            tnew = th[6 * k + lane] - a.prm.lr * mhat / (sqrt(vhat) + a.prm.eps);
+            tnew = th[6 * k + tid] - a.prm.lr * mhat / (sqrt(vhat) + a.prm.eps);
         }
         a.theta_next[e] = tnew;
+        tn_sh[tid] = tnew;
     }
+    __syncthreads();
     double tn[6];
 #pragma unroll
-    for (int d = 0; d < 6; ++d) tn[d] = __shfl(tnew, d);
-    // the new pose (every lane computes the same bits) and this particle's
+    for (int d = 0; d < 6; ++d) tn[d] = tn_sh[d];
+    // the new pose (every thread computes the same bits) and this particle's
     // queries of the next iteration
     Pose P;
     pose_from_theta(tn, &P);
-    if (lane == 0) a.pose[p * K + k] = P;
-    if (k == 0 && lane == 0) a.step_next[p] = a.step[p] + 1;   // read only by the next iteration
+    if (tid == 0) a.pose[p * K + k] = P;
+    if (k == 0 && tid == 0) a.step_next[p] = a.step[p] + 1;   // read only by the next iteration
     const int64_t row = (a.step[p] + 1) % a.rows;
     const int32_t* __restrict__ srow = a.sched + pd.sched_off + row * a.m;
-    for (int i0 = lane; i0 < a.m; i0 += 4 * kWave) {
+    for (int i0 = tid; i0 < a.m; i0 += 4 * kPhiThreads) {
         int32_t si[4];
         float4 sp[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) si[u] = i0 + u * kWave < a.m ? srow[i0 + u * kWave] : 0;
+        for (int u = 0; u < 4; ++u) si[u] = i0 + u * kPhiThreads < a.m ? srow[i0 + u * kPhiThreads] : 0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) sp[u] = a.src4[pd.src_off + si[u]];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (i0 + u * kWave < a.m) a.queries[pd.q_off + (int64_t)k * a.m + i0 + u * kWave] = make_query(&P, sp[u]);
+            if (i0 + u * kPhiThreads < a.m)
+                a.queries[pd.q_off + (int64_t)k * a.m + i0 + u * kPhiThreads] = make_query(&P, sp[u]);
     }
 }
 
