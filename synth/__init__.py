@@ -16,4 +16,14 @@ from .clouds import (  # noqa: F401
     minibatch_schedule,
     rng_streams,
 )
-from .workloads import WORKLOADS, Problem, make_problem, batched_problems, MonteCarlo, mc_problem  # noqa: F401
+from .workloads import (  # noqa: F401
+    MC_HALF_ROT,
+    MC_HALF_TRANS,
+    MC_SEED,
+    WORKLOADS,
+    MonteCarlo,
+    Problem,
+    batched_problems,
+    make_problem,
+    mc_problem,
+)
