@@ -73,9 +73,11 @@ __device__ __forceinline__ void split3(float x, uint16_t& h, uint16_t& m, uint16
 constexpr uint16_t kBf16One = 0x3F80;
 constexpr uint16_t kBf16Zero = 0;
 
-// The eight K slots 8 s .. 8 s + 7 of one side. `ref` selects the A (reference)
-// or B (query) column of the slot table above.
-__device__ __forceinline__ u16x8_t slot_fragment(const float c[3], bool ref, int s)
+// The two fragments of one side for the lane half h of a 32 x 32 x 16
+// product pair: K slots 8 h .. 8 h + 7 (first product) and 16 + 8 h .. +7
+// (second). `ref` selects the A (reference) or B (query) column of the slot
+// table above.
+__device__ __forceinline__ void slot_fragments(const float c[3], bool ref, int hh, u16x8_t& v0, u16x8_t& v1)
 {
 #pragma clang fp contract(off)
     uint16_t h[3], m[3], l[3], nh, nm, nl;
@@ -101,16 +103,11 @@ __device__ __forceinline__ u16x8_t slot_fragment(const float c[3], bool ref, int
         t[21] = nh; t[22] = nm; t[23] = nl;
     }
     for (int k = 24; k < 32; ++k) t[k] = kBf16Zero;
-    u16x8_t v;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        uint16_t x = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (s == q) x = t[8 * q + k];
-        v[k] = x;
+        v0[k] = hh ? t[8 + k] : t[k];
+        v1[k] = hh ? t[24 + k] : t[16 + k];
     }
-    return v;
 }
 
 constexpr int kBlk = kRefPad;   // references per block of the screen (the A operand's 32 rows)
@@ -137,9 +134,11 @@ __global__ void pack_bf16_refs_kernel(const PairDesc* __restrict__ pairs, const 
         c[1] = r.y - pd.c0[1];
         c[2] = r.z - pd.c0[2];
     }
+    u16x8_t v0, v1;
+    slot_fragments(c, true, lane >> 5, v0, v1);
     uint4* out = apack + pd.apack_off + (blk * kWave + lane) * 2;
-    out[0] = __builtin_bit_cast(uint4, slot_fragment(c, true, lane >> 5));
-    out[1] = __builtin_bit_cast(uint4, slot_fragment(c, true, 2 + (lane >> 5)));
+    out[0] = __builtin_bit_cast(uint4, v0);
+    out[1] = __builtin_bit_cast(uint4, v1);
 }
 
 
@@ -168,8 +167,10 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
             c[1] = qf.y - pd.c0[1];
             c[2] = qf.z - pd.c0[2];
         }
-        b0[g] = __builtin_bit_cast(bf16x8_t, slot_fragment(c, false, h));
-        b1[g] = __builtin_bit_cast(bf16x8_t, slot_fragment(c, false, 2 + h));
+        u16x8_t v0, v1;
+        slot_fragments(c, false, h, v0, v1);
+        b0[g] = __builtin_bit_cast(bf16x8_t, v0);
+        b1[g] = __builtin_bit_cast(bf16x8_t, v1);
     }
 
     const int64_t c0 = (int64_t)w.chunk * pd.chunk;
