@@ -9,8 +9,10 @@
 // residual e = s' - r and the six contributions e and e^T (dR/dtheta_d) s,
 // accumulating in FP64. With the point-to-plane metric e is first replaced by
 // its projection rho n on the matched reference's unit normal n
-// (rho = n^T e), which gives rho n and rho n^T (dR/dtheta_d) s. The group's 512 partial sums are combined by a
-// fixed-shape tree in LDS, so the result does not depend on scheduling.
+// (rho = n^T e), which gives rho n and rho n^T (dR/dtheta_d) s. The
+// group's partial sums are combined by a fixed-shape tree (shuffles within
+// each wavefront, then the wavefronts in order), so the result does not
+// depend on scheduling.
 #pragma once
 
 #include "common.hpp"
@@ -37,11 +39,10 @@ constexpr int kGradGroups = 2;   // particles per 1024-thread workgroup, kGradTh
 
 // Gradient of particle pk (global index over pairs, pk < nparticles) by the
 // group `grp` of kGradThreads threads (lt = thread within the group); red is
-// the workgroup's 6 x (kGradGroups kGradThreads) FP64 LDS tree. Every thread
-// of the workgroup takes part in the tree's barriers, also for pk >= n.
+// the workgroup's LDS for the wavefront sums (6 FP64 per wavefront). Every
+// thread of the workgroup takes part in the barrier, also for pk >= n.
 __device__ __forceinline__ void grad_group(const GradArgs& a, int64_t pk, int64_t n, int grp, int lt, double* red)
 {
-    constexpr int W = kGradGroups * kGradThreads;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const bool live = pk < n;
     int64_t p = 0, k = 0;
@@ -54,11 +55,15 @@ __device__ __forceinline__ void grad_group(const GradArgs& a, int64_t pk, int64_
         const Pose* __restrict__ P = a.pose + pk;
         for (int i = lt; i < a.m; i += kGradThreads) {
             const int64_t qi = k * a.m + i;
-            const uint64_t key = min_chunk_keys(a.partial + pd.part_off + qi, pd.chunks, pd.part_stride);
-            const int32_t j = resolve_key(key, a.queries[pd.q_off + qi], a.ref4 + pd.ref_off, pd.n_ref_pad);
-            a.match[p * nq + qi] = j;
+            // the loads that do not depend on the match go first, so that
+            // their latency overlaps the key's; the match is stored after
+            // the last load
             const float4 s = a.src4[pd.src_off + a.sched[pd.sched_off + row * a.m + i]];
+            const float4 qf = a.queries[pd.q_off + qi];
+            const uint64_t key = min_chunk_keys(a.partial + pd.part_off + qi, pd.chunks, pd.part_stride);
+            const int32_t j = resolve_key(key, qf, a.ref4 + pd.ref_off, pd.n_ref_pad);
             const float4 r = a.ref4[pd.ref_off + j];
+            a.match[p * nq + qi] = j;
             double q[3];
             transform_f64(P->R, P->u, s.x, s.y, s.z, q);
             {
@@ -90,18 +95,32 @@ __device__ __forceinline__ void grad_group(const GradArgs& a, int64_t pk, int64_
             }
         }
     }
-    double* r0 = red + grp * kGradThreads;
+    // fixed-shape reduction: a shuffle tree inside each wavefront, then the
+    // group's wavefronts in order (one barrier)
 #pragma unroll
-    for (int d = 0; d < 6; ++d) r0[d * W + lt] = acc[d];
-    __syncthreads();
-    for (int w = kGradThreads / 2; w > 0; w >>= 1) {
-        if (lt < w) {
+    for (int d = 0; d < 6; ++d) {
+        double x = acc[d];
 #pragma unroll
-            for (int d = 0; d < 6; ++d) r0[d * W + lt] += r0[d * W + lt + w];
-        }
-        __syncthreads();
+        for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        acc[d] = x;
     }
-    if (live && lt < 6) a.gbar[pk * 6 + lt] = r0[lt * W] / (double)a.m;
+    constexpr int WV = kGradThreads / kWave;   // wavefronts per group
+    double* r0 = red + grp * WV * 6;
+    const int wv = lt / kWave, lane = lt % kWave;
+    if (lane < 6) {
+        double v = 0.0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d)
+            if (lane == d) v = acc[d];
+        r0[wv * 6 + lane] = v;
+    }
+    __syncthreads();
+    if (live && lt < 6) {
+        double sum = r0[lt];
+#pragma unroll
+        for (int v = 1; v < WV; ++v) sum += r0[v * 6 + lt];
+        a.gbar[pk * 6 + lt] = sum / (double)a.m;
+    }
 }
 
 }  // namespace sicp

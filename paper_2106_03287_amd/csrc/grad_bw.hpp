@@ -17,7 +17,7 @@ inline size_t grad_bw_lds_bytes(int K)
 {
     const size_t sel = (sizeof(SelectShared) + 15) / 16 * 16;
     const size_t bw = sel + bandwidth_lds_bytes(K);
-    const size_t gr = sizeof(double) * 6 * kGradGroups * kGradThreads;
+    const size_t gr = sizeof(double) * 6 * kGradGroups * (kGradThreads / kWave);
     return bw > gr ? bw : gr;
 }
 
