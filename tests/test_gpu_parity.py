@@ -450,3 +450,50 @@ def test_bf16_solver_equals_the_fp32_solver_bitwise():
         np.testing.assert_array_equal(runs[S.NN_BF16_RERANK][0], od["match"])
         np.testing.assert_array_equal(runs[S.NN_BF16_RERANK][0], runs[S.NN_FP32][0])
         np.testing.assert_array_equal(runs[S.NN_BF16_RERANK][1], runs[S.NN_FP32][1])
+
+
+# ------------------------------------------------------------------ the bench's launch shapes
+
+def _pinned(workload, nn):
+    import bench
+    return tuple(int(x) for x in bench.PINNED_TILING[(workload, nn)].split(","))
+
+
+def test_kinect_full_solve_at_the_bench_shapes_bf16_equals_fp32_and_oracle():
+    """The benched Kinect solve (K 100, m 300, M 20,000, T 200) with the
+    pinned NN shape of each search mode: both give the same particles bit
+    for bit, within the pose bar of the oracle's solve."""
+    prob = synth.make_problem("kinect", 0)
+    print(f"kinect full solve at bench shapes: T={prob.T}", flush=True)
+    out = {}
+    for nn, mode in (("bf16", S.NN_BF16_RERANK), ("fp32", S.NN_FP32)):
+        gcfg, _ = both_configs(prob)
+        gcfg.nn_mode = mode
+        sol = S.SteinICP(gcfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule))
+        sol.set_tiling(*_pinned("kinect", nn))
+        sol.step(prob.T)
+        out[nn] = sol.particles().cpu().numpy()[0]
+        sol.close()
+    np.testing.assert_array_equal(out["bf16"], out["fp32"])
+    assert_poses_close(out["bf16"], oracle_run(prob, prob.T))
+
+
+@pytest.mark.parametrize("nn", ["bf16", "fp32"])
+def test_lidar_full_size_iteration_at_the_bench_shape(nn):
+    """One LiDAR iteration (K 300, m 1000, M 100,000) with the pinned NN shape
+    the bench times, against the oracle (matches bit-exact)."""
+    prob = synth.make_problem("lidar", 0, T=1)
+    print(f"lidar full-size iteration at the bench shape ({nn})", flush=True)
+    gcfg, ocfg = both_configs(prob)
+    gcfg.nn_mode = S.NN_BF16_RERANK if nn == "bf16" else S.NN_FP32
+    sol = S.SteinICP(gcfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule))
+    sol.set_tiling(*_pinned("lidar", nn))
+    sol.step(1)
+    diag = {k: v.cpu().numpy()[0] for k, v in sol.diagnostics().items()}
+    th = sol.particles().cpu().numpy()[0]
+    sol.close()
+    st = oracle.State(prob.theta0)
+    od = oracle.step(ocfg, prob.pair.src, prob.pair.ref, prob.schedule[0], st)
+    np.testing.assert_array_equal(diag["match"], od["match"])
+    np.testing.assert_allclose(diag["gbar"], od["gbar"], rtol=STEP_RTOL, atol=1e-13)
+    np.testing.assert_allclose(th, st.theta, rtol=0, atol=1e-11)
