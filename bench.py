@@ -30,6 +30,36 @@ NN_SOURCES = ["paper_2106_03287_amd/csrc/nn.hpp", "paper_2106_03287_amd/csrc/com
 NN_BF16_SOURCES = NN_SOURCES + ["paper_2106_03287_amd/csrc/nn_bf16.hpp"]
 
 
+def host_info():
+    """Device, HIP and host CPU, and the GPU's clocks and power as found
+    (rocm-smi, run as a child process; any field it cannot give is None)."""
+    import subprocess
+    import torch
+    info = {"gpu": None, "hip": getattr(torch.version, "hip", None), "torch": torch.__version__,
+            "cpu_model": None, "cpu_threads": os.cpu_count(), "rocm_smi": None}
+    try:
+        info["gpu"] = torch.cuda.get_device_name(0)
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--json"], capture_output=True, text=True,
+                           timeout=20)
+        card = next(iter(json.loads(r.stdout).values()))
+        info["rocm_smi"] = {k: v for k, v in card.items()
+                            if any(w in k.lower() for w in ("sclk", "mclk", "fclk", "power"))}
+    except Exception:
+        pass
+    return info
+
+
 def nn_source_sha(nn="fp32"):
     import hashlib
     h = hashlib.sha256()
@@ -273,6 +303,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, plane=args.metric == "plane")
+    out["host"] = host_info()
     print(json.dumps(out), flush=True)
 
 
@@ -364,6 +395,7 @@ def run_batched(args):
     for s_ in singles:
         s_.close()
     batch.close()
+    out["host"] = host_info()
     print(json.dumps(out), flush=True)
 
 
@@ -486,6 +518,7 @@ def run_mc(args):
         out["cpu_baseline"] = cpu_baseline_mc(prob, T)
     mc.close()
     stein.close()
+    out["host"] = host_info()
     print(json.dumps(out), flush=True)
 
 
@@ -563,6 +596,7 @@ def run_proposal(args):
                      "flops_per_pair": 2 * PROPOSAL_MACS_PER_PAIR, "avg_ms_per_pair": round(net_ms / n, 5)},
     }
     model.close()
+    out["host"] = host_info()
     print(json.dumps(out), flush=True)
 
 
