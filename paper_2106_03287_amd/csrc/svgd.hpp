@@ -535,6 +535,23 @@ __global__ __launch_bounds__(kPhiThreads) void svgd_phi_update_kernel(SvgdArgs a
     double tk[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) tk[d] = th[6 * k + d];
+    // what does not depend on the new particle goes first, so that its
+    // latency overlaps the sums: this thread's minibatch points of the next
+    // iteration (m <= 4 kPhiThreads per pass) and Adam's bias corrections
+    const int64_t row = (a.step[p] + 1) % a.rows;
+    const int32_t* __restrict__ srow = a.sched + pd.sched_off + row * a.m;
+    float4 sp0[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = tid + u * kPhiThreads;
+        sp0[u] = i < a.m ? a.src4[pd.src_off + srow[i]] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    double bc1 = 1.0, bc2 = 1.0;
+    if (tid < 6 && a.prm.optimizer != 1) {
+        const double t_new = (double)(a.step[p] + 1);
+        bc1 = 1.0 - pow(a.prm.beta1, t_new);
+        bc2 = 1.0 - pow(a.prm.beta2, t_new);
+    }
 
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int l = tid; l < K; l += kPhiThreads) {
@@ -592,9 +609,6 @@ __global__ __launch_bounds__(kPhiThreads) void svgd_phi_update_kernel(SvgdArgs a
         if (a.prm.optimizer == 1) {
             tnew = th[6 * k + tid] + a.prm.lr * phi_d;
         } else {
-            const double t_new = (double)(a.step[p] + 1);
-            const double bc1 = 1.0 - pow(a.prm.beta1, t_new);
-            const double bc2 = 1.0 - pow(a.prm.beta2, t_new);
             const double g = -phi_d;
             const double mm = a.prm.beta1 * a.mom[e] + (1.0 - a.prm.beta1) * g;
             const double vv = a.prm.beta2 * a.vel[e] + (1.0 - a.prm.beta2) * (g * g);
@@ -617,9 +631,12 @@ __global__ __launch_bounds__(kPhiThreads) void svgd_phi_update_kernel(SvgdArgs a
     pose_from_theta(tn, &P);
     if (tid == 0) a.pose[p * K + k] = P;
     if (k == 0 && tid == 0) a.step_next[p] = a.step[p] + 1;   // read only by the next iteration
-    const int64_t row = (a.step[p] + 1) % a.rows;
-    const int32_t* __restrict__ srow = a.sched + pd.sched_off + row * a.m;
-    for (int i0 = tid; i0 < a.m; i0 += 4 * kPhiThreads) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = tid + u * kPhiThreads;
+        if (i < a.m) a.queries[pd.q_off + (int64_t)k * a.m + i] = make_query(&P, sp0[u]);
+    }
+    for (int i0 = tid + 4 * kPhiThreads; i0 < a.m; i0 += 4 * kPhiThreads) {   // m > 1024
         int32_t si[4];
         float4 sp[4];
 #pragma unroll
