@@ -111,9 +111,10 @@ def cpu_baseline(prob, budget_s=15.0, plane=False):
 # (full solves, median of 3); the runner-up shapes are within 2 %
 # search mode of --nn auto: the certified BF16 screen returns the FP32 search's
 # answers bit for bit; measured faster than the FP32 search on the Kinect
-# (1.25x on the NN stage) and LiDAR (1.37x) workloads, slower on the small
-# cuboid clouds, where the search is latency-bound
-AUTO_NN = {"cuboid": "fp32", "kinect": "bf16", "lidar": "bf16", "mc": "bf16"}
+# (1.56x on the NN launch), LiDAR (1.38x), batched (1.5x) and Monte-Carlo
+# workloads, and not on the small cuboid clouds, where the search is
+# latency-bound
+AUTO_NN = {"cuboid": "fp32", "kinect": "bf16", "lidar": "bf16", "mc": "bf16", "batched": "bf16"}
 
 PINNED_TILING = {
     ("kinect", "fp32"): "4,16,2048,2",
@@ -324,7 +325,8 @@ def run_batched(args):
     scheds = [dev(p.schedule) for p in probs]
     th0 = dev(np.stack([p.theta0 for p in probs]))
     cfg = S.stein_icp_default_config(num_particles=K, batch_size=m, schedule_rows=probs[0].schedule.shape[0],
-                                     lr=probs[0].lr, autotune=0 if args.tiling else args.autotune)
+                                     lr=probs[0].lr, autotune=0 if args.tiling else args.autotune,
+                                     nn_mode=S.NN_BF16_RERANK if args.nn == "bf16" else S.NN_FP32)
     t_init = time.perf_counter()
     batch = S.SteinICP.batch(cfg, srcs, refs, th0, scheds)
     init_ms = (time.perf_counter() - t_init) * 1e3
@@ -362,6 +364,15 @@ def run_batched(args):
     nn_ms = batch.time_nn(20)
     pairs_per_launch = sum(K * m * len(p.pair.ref) for p in probs)
     achieved = pairs_per_launch * FLOPS_PER_PAIR / (nn_ms * 1e-3) / 1e12
+    if args.nn == "bf16":
+        mfma = pairs_per_launch * 64 / (nn_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "achieved": round(mfma, 3), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(mfma / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None, "kernel": "nn_bf16_kernel",
+                    "avg_launch_ms": round(nn_ms, 5), "pair_evals_per_launch": pairs_per_launch}
+    else:
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None, "kernel": "nn_fp32_kernel",
+                    "avg_launch_ms": round(nn_ms, 5), "pair_evals_per_launch": pairs_per_launch}
     value = P * T / (ms_b / 1e3)
     out = {
         "metric": METRIC,
@@ -374,12 +385,12 @@ def run_batched(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16+f32" if args.nn == "bf16" else "f32",
         "data": "synthetic",
         "config": {"workload": "batched", "pairs": P, "K": K, "m": m, "T": T,
                    "M_range": [min(len(p.pair.ref) for p in probs), max(len(p.pair.ref) for p in probs)],
                    "N_range": [min(len(p.pair.src) for p in probs), max(len(p.pair.src) for p in probs)],
-                   "nn": "fp32", "step": "one batched solve of all pairs, T iterations"},
+                   "nn": args.nn, "step": "one batched solve of all pairs, T iterations"},
         "sequential_ms": round(ms_s, 3),
         "sequential_pair_iters_per_s": round(P * T / (ms_s / 1e3), 2),
         "speedup_vs_sequential": round(ms_s / ms_b, 3),
@@ -387,10 +398,7 @@ def run_batched(args):
         "stage_ms_per_iter": {k: round(v / T, 5) for k, v in stage.items()},
         "init_ms": round(init_ms, 2),
         "nn_tiling": tiling,
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
-                     "kernel": "nn_fp32_kernel", "avg_launch_ms": round(nn_ms, 5),
-                     "pair_evals_per_launch": pairs_per_launch},
+        "roofline": roofline,
     }
     for s_ in singles:
         s_.close()

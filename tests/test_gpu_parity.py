@@ -497,3 +497,19 @@ def test_lidar_full_size_iteration_at_the_bench_shape(nn):
     np.testing.assert_array_equal(diag["match"], od["match"])
     np.testing.assert_allclose(diag["gbar"], od["gbar"], rtol=STEP_RTOL, atol=1e-13)
     np.testing.assert_allclose(th, st.theta, rtol=0, atol=1e-11)
+
+
+def test_batched_uneven_pairs_bf16_equals_fp32_bitwise():
+    """Uneven pairs in one batch: the certified BF16 search gives the FP32
+    search's particles bit for bit."""
+    probs = synth.batched_problems(6, K=16, m=40, T=8, size_scale=0.3)
+    out = {}
+    for mode in (S.NN_FP32, S.NN_BF16_RERANK):
+        gcfg, _ = both_configs(probs[0])
+        gcfg.nn_mode = mode
+        b = S.SteinICP.batch(gcfg, [dev(p.pair.src) for p in probs], [dev(p.pair.ref) for p in probs],
+                             dev(np.stack([p.theta0 for p in probs])), [dev(p.schedule) for p in probs])
+        b.step(8)
+        out[mode] = b.particles().cpu().numpy()
+        b.close()
+    np.testing.assert_array_equal(out[S.NN_BF16_RERANK], out[S.NN_FP32])
