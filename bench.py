@@ -591,9 +591,10 @@ def run_proposal(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16 network, f32/f64 Stein ICP",
+        "dtype": "bf16 network, bf16+f32 search and f64 Stein ICP (proposal); f32 search (plain)",
         "data": "synthetic",
         "config": {"workload": "proposal", "pairs": n, "K": 100, "T_plain": 300, "T_proposal": 30,
+                   "nn_proposal": "bf16", "nn_plain": "fp32",
                    "step": "network on every pair, then 30 batched Stein iterations"},
         "plain_300_pairs_per_s": round(n / (plain_ms / 1e3), 2),
         "speedup_vs_plain_300": round(plain_ms / prop_ms, 3),
