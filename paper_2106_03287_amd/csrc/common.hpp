@@ -31,7 +31,7 @@ struct PairDesc {
     int64_t part_stride;  // distance between a query's chunk keys (queries of its NN group)
     float c0[4];        // reference centroid (centres the BF16 screen)
     int32_t chunks;     // reference chunks, one partial argmin each
-    int32_t chunk;      // references per chunk (multiple of 4 * kTile)
+    int32_t chunk;      // references per chunk (multiple of kRefPad)
     int32_t qblocks;    // query blocks of kWave * Q queries
     int32_t pad_;
 };
