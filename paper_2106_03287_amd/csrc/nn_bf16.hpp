@@ -175,9 +175,10 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
 
     const int64_t c0 = (int64_t)w.chunk * pd.chunk;
     const int64_t cend = min(c0 + (int64_t)pd.chunk, pd.n_ref_pad);
-    const int64_t nblk = (cend - c0) / kBlk;
-    const int64_t t0 = (nblk * wave) / W;
-    const int64_t t1 = (nblk * (wave + 1)) / W;
+    // the wavefront's block range [t0, t1) of the chunk (wave-uniform)
+    const int32_t nblk = (int32_t)((cend - c0) / kBlk);
+    const int32_t t0 = uniform((int32_t)(((int64_t)nblk * wave) / W));
+    const int32_t t1 = uniform((int32_t)(((int64_t)nblk * (wave + 1)) / W));
     const uint4* __restrict__ ap = a.apack + pd.apack_off + ((c0 / kBlk) * kWave + lane) * 2;
 
     float best[G], sec[G];   // best block minimum, and the smallest of the other blocks
@@ -186,24 +187,11 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     for (int g = 0; g < G; ++g) {
         best[g] = __builtin_inff();
         sec[g] = __builtin_inff();
-        bblk[g] = (int32_t)t0;
+        bblk[g] = t0;
     }
-    uint4 an0 = make_uint4(0u, 0u, 0u, 0u), an1 = an0;
-    if (t0 < t1) {
-        an0 = ap[t0 * 2 * kWave];
-        an1 = ap[t0 * 2 * kWave + 1];
-    }
-    for (int64_t tt = t0; tt < t1; ++tt) {
-        const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, an0);
-        const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, an1);
-        if (tt + 1 < t1) {   // next block's fragments in flight
-            an0 = ap[(tt + 1) * 2 * kWave];
-            an1 = ap[(tt + 1) * 2 * kWave + 1];
-        }
-        // all groups' first products, then their second ones (independent
-        // accumulators keep the matrix pipeline busy), then the minimum
-        // epilogues
-        f32x16_t acc[G];
+    const auto products = [&](const uint4& f0, const uint4& f1, f32x16_t (&acc)[G]) {
+        const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, f0);
+        const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, f1);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
 #pragma unroll
@@ -212,18 +200,70 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1[g], acc[g], 0, 0, 0);
+    };
+    // minimum of the lane's sixteen values of block blk; the new second
+    // smallest block minimum is the median of (best, sec, mn) as best <= sec
+    const auto take_min = [&](const f32x16_t (&acc)[G], int32_t blk) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            float m4[4];
+            float mn = __builtin_fminf(__builtin_fminf(acc[g][0], acc[g][1]), acc[g][2]);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                m4[i] = __builtin_fminf(__builtin_fminf(acc[g][4 * i], acc[g][4 * i + 1]),
-                                        __builtin_fminf(acc[g][4 * i + 2], acc[g][4 * i + 3]));
-            const float mn = __builtin_fminf(__builtin_fminf(m4[0], m4[1]), __builtin_fminf(m4[2], m4[3]));
-            sec[g] = __builtin_fminf(sec[g], __builtin_fmaxf(best[g], mn));
+            for (int t = 3; t < 15; t += 2) mn = __builtin_fminf(__builtin_fminf(mn, acc[g][t]), acc[g][t + 1]);
+            mn = __builtin_fminf(mn, acc[g][15]);
+            sec[g] = __builtin_amdgcn_fmed3f(best[g], sec[g], mn);
             const bool better = mn < best[g];
             best[g] = better ? mn : best[g];
-            bblk[g] = better ? (int32_t)tt : bblk[g];
+            bblk[g] = better ? blk : bblk[g];
+        }
+    };
+    // fragments of block blk, clamped into the range (loads past its end
+    // re-read its last block)
+    const auto frag = [&](int32_t blk, uint4& f0, uint4& f1) {
+        const int32_t b = min(blk, t1 - 1);
+        f0 = ap[(int64_t)b * 2 * kWave];
+        f1 = ap[(int64_t)b * 2 * kWave + 1];
+    };
+    if constexpr (G >= 4) {
+        // Software pipeline: the products of block b are issued before the
+        // minimum of block b - 1 is taken, so the matrix pipeline and the
+        // vector ALU work on different blocks (two accumulator sets); two
+        // fragment buffers keep the next blocks' loads in flight.
+        if (t0 < t1) {
+            uint4 fa0, fa1, fb0, fb1;
+            f32x16_t accp[G], accc[G];
+            frag(t0, fa0, fa1);
+            frag(t0 + 1, fb0, fb1);
+            products(fa0, fa1, accp);   // block t0
+            frag(t0 + 2, fa0, fa1);
+            int32_t b = t0 + 1;
+            // fb holds block b and fa block b + 1 at the top of every trip
+            for (; b + 1 < t1; b += 2) {
+                products(fb0, fb1, accc);   // block b
+                frag(b + 2, fb0, fb1);
+                take_min(accp, b - 1);
+                products(fa0, fa1, accp);   // block b + 1
+                frag(b + 3, fa0, fa1);
+                take_min(accc, b);
+            }
+            if (b < t1) {
+                products(fb0, fb1, accc);   // block b = t1 - 1
+                take_min(accp, b - 1);
+                take_min(accc, b);
+            } else {
+                take_min(accp, b - 1);
+            }
+        }
+    } else {
+        // one block per trip, the next block's fragments in flight (fewer
+        // registers: four wavefronts per SIMD fit)
+        uint4 f0 = make_uint4(0u, 0u, 0u, 0u), f1 = f0;
+        if (t0 < t1) frag(t0, f0, f1);
+        for (int32_t b = t0; b < t1; ++b) {
+            const uint4 c0f = f0, c1f = f1;
+            frag(b + 1, f0, f1);
+            f32x16_t acc[G];
+            products(c0f, c1f, acc);
+            take_min(acc, b);
         }
     }
 
@@ -316,7 +356,7 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
 }
 
 template <int Q, int W>
-__global__ __launch_bounds__(kWave * W) void nn_bf16_kernel(NNBf16Args a)
+__global__ __launch_bounds__(kWave * W, (Q == 1 && W == 8) ? 4 : 1) void nn_bf16_kernel(NNBf16Args a)
 {
     __shared__ uint64_t sk[W][kWave * Q];
     for (int64_t it = blockIdx.x; it < a.nwork; it += gridDim.x) nn_bf16_item<Q, W>(a, a.work[it], sk);
