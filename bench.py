@@ -120,7 +120,7 @@ PINNED_TILING = {
     ("kinect", "fp32"): "4,16,2048,2",
     ("kinect", "bf16"): "2,8,20096,0",
     ("lidar", "fp32"): "4,8,4096,0",
-    ("lidar", "bf16"): "1,8,25088,0",
+    ("lidar", "bf16"): "2,8,25088,0",
 }
 
 

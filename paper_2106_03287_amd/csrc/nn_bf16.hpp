@@ -118,7 +118,10 @@ __device__ __forceinline__ int blk_row(int t, int h) { return 8 * (t >> 2) + 4 *
 
 // grid (blocks of 32 references / 4, groups) x 256 threads, one wavefront
 // per block: each lane's two A fragments (K slots 8 h .. 8 h + 7 and
-// 16 + 8 h .. +7 of row lane % 32), 32 bytes per lane and block.
+// 16 + 8 h .. +7 of row lane % 32). A block takes 128 uint4: the 64 lanes'
+// first fragments, then their second ones, so a wavefront reads each as
+// one contiguous row. (The second fragments of lanes 32..63 hold K slots
+// 24..31, which the queries' fragments zero.)
 __global__ void pack_bf16_refs_kernel(const PairDesc* __restrict__ pairs, const float4* __restrict__ ref4,
                                       uint4* __restrict__ apack)
 {
@@ -136,9 +139,9 @@ __global__ void pack_bf16_refs_kernel(const PairDesc* __restrict__ pairs, const 
     }
     u16x8_t v0, v1;
     slot_fragments(c, true, lane >> 5, v0, v1);
-    uint4* out = apack + pd.apack_off + (blk * kWave + lane) * 2;
+    uint4* out = apack + pd.apack_off + blk * 2 * kWave + lane;
     out[0] = __builtin_bit_cast(uint4, v0);
-    out[1] = __builtin_bit_cast(uint4, v1);
+    out[kWave] = __builtin_bit_cast(uint4, v1);
 }
 
 
@@ -179,7 +182,8 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     const int32_t nblk = (int32_t)((cend - c0) / kBlk);
     const int32_t t0 = uniform((int32_t)(((int64_t)nblk * wave) / W));
     const int32_t t1 = uniform((int32_t)(((int64_t)nblk * (wave + 1)) / W));
-    const uint4* __restrict__ ap = a.apack + pd.apack_off + ((c0 / kBlk) * kWave + lane) * 2;
+    const uint4* __restrict__ ap0 = a.apack + pd.apack_off + (c0 / kBlk) * 2 * kWave + lane;
+    const uint4* __restrict__ ap1 = a.apack + pd.apack_off + (c0 / kBlk) * 2 * kWave + kWave + j;
 
     float best[G], sec[G];   // best block minimum, and the smallest of the other blocks
     int32_t bblk[G];
@@ -217,11 +221,14 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
         }
     };
     // fragments of block blk, clamped into the range (loads past its end
-    // re-read its last block)
+    // re-read its last block). The second fragment of lane l + 32 meets
+    // the queries' zero K slots 24..31, so it is read from lane l's
+    // (finite BF16 values, products exactly zero): the wavefront's second
+    // load touches 512 bytes instead of 1 KB.
     const auto frag = [&](int32_t blk, uint4& f0, uint4& f1) {
         const int32_t b = min(blk, t1 - 1);
-        f0 = ap[(int64_t)b * 2 * kWave];
-        f1 = ap[(int64_t)b * 2 * kWave + 1];
+        f0 = ap0[(int64_t)b * 2 * kWave];
+        f1 = ap1[(int64_t)b * 2 * kWave];
     };
     if constexpr (G >= 4) {
         // Software pipeline: the products of block b are issued before the
@@ -238,12 +245,16 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
             int32_t b = t0 + 1;
             // fb holds block b and fa block b + 1 at the top of every trip
             for (; b + 1 < t1; b += 2) {
+                // (the scheduling barriers keep each refill in the half
+                // trip that consumed its buffer: two blocks of latency)
                 products(fb0, fb1, accc);   // block b
                 frag(b + 2, fb0, fb1);
                 take_min(accp, b - 1);
+                __builtin_amdgcn_sched_barrier(0);
                 products(fa0, fa1, accp);   // block b + 1
                 frag(b + 3, fa0, fa1);
                 take_min(accc, b);
+                __builtin_amdgcn_sched_barrier(0);
             }
             if (b < t1) {
                 products(fb0, fb1, accc);   // block b = t1 - 1
@@ -254,16 +265,29 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
             }
         }
     } else {
-        // one block per trip, the next block's fragments in flight (fewer
-        // registers: four wavefronts per SIMD fit)
-        uint4 f0 = make_uint4(0u, 0u, 0u, 0u), f1 = f0;
-        if (t0 < t1) frag(t0, f0, f1);
-        for (int32_t b = t0; b < t1; ++b) {
-            const uint4 c0f = f0, c1f = f1;
-            frag(b + 1, f0, f1);
+        // one accumulator set (fewer registers: four wavefronts per SIMD
+        // fit); two fragment buffers, each refilled with the block two ahead
+        // as soon as its products are issued
+        if (t0 < t1) {
+            uint4 fa0, fa1, fb0, fb1;
             f32x16_t acc[G];
-            products(c0f, c1f, acc);
-            take_min(acc, b);
+            frag(t0, fa0, fa1);
+            frag(t0 + 1, fb0, fb1);
+            int32_t b = t0;
+            for (; b + 1 < t1; b += 2) {
+                products(fa0, fa1, acc);   // block b
+                frag(b + 2, fa0, fa1);
+                take_min(acc, b);
+                __builtin_amdgcn_sched_barrier(0);
+                products(fb0, fb1, acc);   // block b + 1
+                frag(b + 3, fb0, fb1);
+                take_min(acc, b + 1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (b < t1) {
+                products(fa0, fa1, acc);   // block b = t1 - 1
+                take_min(acc, b);
+            }
         }
     }
 
@@ -310,6 +334,9 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     if (t0 < t1) {
         constexpr double u = 0x1.0p-24;
         const int64_t nref = 16 * (t1 - t0);
+        // gathers kept in flight together (one query per lane: the
+        // unrolled loop's registers would cost occupancy)
+        constexpr int kRescanUnroll = Q == 1 ? 1 : 4;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int64_t qi = qbase + 32 * g + j;
@@ -336,6 +363,7 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
                 const int fj = b & 31, fh = b >> 5;
                 const float4 qf = a.queries[pd.q_off + qbase + 32 * g + fj];
                 uint64_t kb = ~0ull;
+#pragma unroll kRescanUnroll
                 for (int64_t e = lane; e < nref; e += kWave) {
                     const int64_t r = c0 + (t0 + e / 16) * kBlk + blk_row((int)(e & 15), fh);
                     const float4 rr = a.ref4[pd.ref_off + r];
