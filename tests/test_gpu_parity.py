@@ -429,6 +429,46 @@ def test_bf16_screen_exact_ties_go_to_the_lowest_index():
     _bf16_check(q, ref)
 
 
+def _grid_problem():
+    """Cloud pair on an integer grid with repeated references: many exact
+    ties between and inside the screen's 32-reference blocks."""
+    rng = np.random.default_rng(41)
+    base = rng.integers(-6, 7, (500, 3)).astype(np.float32)
+    ref = np.concatenate([base, base[rng.permutation(500)], base[::-1]])
+    src = (rng.integers(-12, 13, (800, 3)) / 2.0).astype(np.float32)
+    K, m, rows = 16, 64, 2
+    theta0 = np.zeros((K, 6))
+    theta0[:, :3] = rng.integers(-2, 3, (K, 3)) / 4.0   # exact translations keep the ties exact
+    sched = synth.minibatch_schedule(41, len(src), m, rows)
+    return src, ref, theta0, sched, K, m, rows
+
+
+@pytest.mark.parametrize("q", [1, 2])
+@pytest.mark.parametrize("w", [4, 8, 16])
+def test_bf16_screen_every_block_count_per_wavefront(q, w):
+    """Chunks of 1 to 89 blocks of 32 references give the wavefronts of a
+    workgroup 0 to 22 blocks each: every trip count of the screen's block
+    loops (the two-buffer loop and the software pipeline, both tails) and
+    ragged last chunks. The first iteration's matches equal the oracle's
+    (lowest index on ties), on the cuboid pair and on an all-ties grid."""
+    prob = synth.make_problem("cuboid", 0, T=1)
+    cases = [(prob.pair.src, prob.pair.ref, prob.theta0, prob.schedule, prob.K, prob.m, prob.schedule.shape[0]),
+             _grid_problem()]
+    for src, ref, theta0, sched, K, m, rows in cases:
+        cfg = S.stein_icp_default_config(num_particles=K, batch_size=m, schedule_rows=rows, autotune=0,
+                                         nn_mode=S.NN_BF16_RERANK)
+        ocfg = oracle.make_config(K, m, len(src), len(ref))
+        want = oracle.step(ocfg, src, ref, sched[0], oracle.State(theta0))["match"]
+        sol = S.SteinICP(cfg, dev(src), dev(ref), dev(theta0), dev(sched))
+        for nb in (1, 2, 3, 5, 8, 13, 21, 34, 55, 89):
+            sol.set_tiling(q, w, 32 * nb)
+            sol.set_state(dev(theta0))
+            sol.step(1)
+            got = sol.diagnostics()["match"].cpu().numpy()[0]
+            assert np.array_equal(got, want), (q, w, nb, int((got != want).sum()))
+        sol.close()
+
+
 def test_bf16_solver_equals_the_fp32_solver_bitwise():
     """With the certified screen the matches are the FP32 search's, so the
     whole solve is bit for bit the FP32 solve (and the first iteration's
