@@ -17,8 +17,8 @@
 // only the minimum of those sixteen values and the block where it fell. The
 // wide product gives each lane sixteen values to reduce per pair of matrix
 // instructions (three-input minimums), where a 16 x 16 product gives four
-// per instruction: the vector-ALU work per distance, which bounded a 16 x 16
-// screen, about halves.
+// per instruction: the vector-ALU work per distance, which bounds the screen,
+// about halves.
 //
 // Rerank: each lane recomputes the exact FP32 distance (the same operation
 // sequence as the FP32 search) of its sixteen references in its best block,
