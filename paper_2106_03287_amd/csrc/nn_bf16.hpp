@@ -352,7 +352,13 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
                     c[2] = qf.z - pd.c0[2];
                 }
                 const double qn = sqrt((double)c[0] * c[0] + (double)c[1] * c[1] + (double)c[2] * c[2]);
-                const double span = (qn + (double)pd.c0[3]) * (1.0 + 0x1.0p-20);
+                // a reference that could match or beat fwg lies within
+                // sqrt(fwg) of the query, so its centred norm is at most
+                // qn + sqrt(fwg) (triangle inequality; the 2^-20 slack
+                // covers the rounding of the centring and of the FP32
+                // distance): that norm, when below R, bounds the error
+                const double rmax = fmin((double)pd.c0[3], qn + sqrt((double)fwg));
+                const double span = (qn + rmax) * (1.0 + 0x1.0p-20);
                 const double margin = 32.0 * u * span * span;
                 fail = !((double)sec[g] - margin > (double)fwg * (1.0 + 8.0 * u));
             }
