@@ -17,8 +17,8 @@
 // only the minimum of those sixteen values and the block where it fell. The
 // wide product gives each lane sixteen values to reduce per pair of matrix
 // instructions (three-input minimums), where a 16 x 16 product gives four
-// per instruction: the vector-ALU work per distance, which bounds the screen,
-// about halves.
+// per instruction: the vector-ALU work per distance, which bounded a 16 x 16
+// screen, about halves.
 //
 // Rerank: each lane recomputes the exact FP32 distance (the same operation
 // sequence as the FP32 search) of its sixteen references in its best block,
@@ -35,8 +35,10 @@
 // difference. Each lane also keeps s2, the smallest block minimum of its
 // rows outside its best block. After the workgroup merges its keys into the
 // chunk minimum F_wg, a lane whose references outside its best block all
-// satisfy F > F_wg -- guaranteed when s2 - 32 u (|q_c| + R)^2 > F_wg (1 + 8 u)
-// -- has lost nothing; otherwise that lane's own rows of its wavefront's
+// satisfy F > F_wg -- guaranteed when s2 - 32 u (|q_c| + R')^2 > F_wg (1 + 8 u)
+// with R' = min(R, |q_c| + sqrt(F_wg)), as only references within sqrt(F_wg)
+// of the query can win -- has lost nothing; otherwise that lane's own rows
+// of its wavefront's
 // blocks are searched again in FP32 by the wavefront and folded into the
 // chunk minimum. The result is the FP32 search's key, ties included.
 #pragma once
