@@ -38,9 +38,9 @@
 // satisfy F > F_wg -- guaranteed when s2 - 32 u (|q_c| + R')^2 > F_wg (1 + 8 u)
 // with R' = min(R, |q_c| + sqrt(F_wg)), as only references within sqrt(F_wg)
 // of the query can win -- has lost nothing; otherwise that lane's own rows
-// of its wavefront's
-// blocks are searched again in FP32 by the wavefront and folded into the
-// chunk minimum. The result is the FP32 search's key, ties included.
+// of its wavefront's blocks are searched again in FP32 by the wavefront and
+// folded into the chunk minimum. The result is the FP32 search's key, ties
+// included.
 #pragma once
 
 #include "common.hpp"
