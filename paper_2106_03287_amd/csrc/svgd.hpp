@@ -7,9 +7,10 @@
 //    kernel of Eq. 17. The median heuristic h = med^2 / ln K needs the middle
 //    order statistics of the K(K-1)/2 distances between distinct particles,
 //    found exactly: the distances are stored as 16-bit monotone keys in LDS
-//    (K up to about 345), a 4096-bin integer histogram of the key range
-//    narrows them to one bin in at most two rounds, and the exact FP64
-//    distances of that bin's few pairs are recomputed and ranked by counting.
+//    (K up to about 345), a 4096-bin integer histogram of the keys' own range
+//    finds the bins of both middle ranks in one pass, and the exact FP64
+//    distances of those bins' few pairs are recomputed and ranked by counting
+//    (wider ranges narrow bin by bin).
 //    Larger K keep FP64 distances in global memory and bin by value. A radix
 //    select over IEEE-754 bit patterns covers the degenerate cases. It
 //    depends only on the particles, so it runs beside the gradients.
@@ -108,7 +109,7 @@ struct SelectShared {
     double wmin[kSvgdWaves], wmax[kSvgdWaves];
     double dres;
     uint64_t u64a, u64b;
-    uint32_t bin, before, count, ncand, found;
+    uint32_t bin, before, count, ncand, found, bin_b, end_b;
 };
 
 // Exact squared distance of upper-triangle pair q from the particles in LDS.
@@ -441,6 +442,137 @@ __device__ inline double select_keyed(const uint16_t* key, int64_t n, int64_t r,
     return select_radix(KeyRunValues{key, n, lo, hi, K, rot, th}, r, sh);
 }
 
+// Ranks ra and rb (rb is ra or ra + 1) of the K(K-1)/2 pair distances
+// whose 16-bit keys are in LDS, in one pass: the keys' own range is binned
+// (one key value per bin when it spans at most 4096 values), one scan finds
+// the bins of both ranks, and the exact FP64 distances of the pairs in those
+// bins (adjacent ranks: nothing lies between them) are ranked by counting.
+// When those bins hold more than kCandCap pairs, select_keyed narrows each
+// rank on its own.
+__device__ inline void select_pair_keyed(const uint16_t* key, int64_t n, int64_t ra, int64_t rb, int K, int rot,
+                                         const double* th, SelectShared& sh, double& va, double& vb)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wave = tid >> 6;
+    uint32_t kmin = 0xffffu, kmax = 0u;
+    for (int64_t q = tid; q < n; q += kSvgdThreads) {
+        const uint32_t x = key[q];
+        kmin = min(kmin, x);
+        kmax = max(kmax, x);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, o));
+        kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, o));
+    }
+    if (lane == 0) sh.wsum[wave] = kmin | (kmax << 16);
+    if (tid == 0) {
+        sh.bin = 0;
+        sh.before = 0;
+        sh.bin_b = 0;
+        sh.end_b = 0;
+    }
+    __syncthreads();
+    uint32_t lo = 0xffffu, hi = 0u;
+    for (int w = 0; w < kSvgdWaves; ++w) {
+        const uint32_t v = sh.wsum[w];
+        lo = min(lo, v & 0xffffu);
+        hi = max(hi, v >> 16);
+    }
+    const uint32_t range = hi - lo + 1;
+    int sft = 0;
+    while ((range - 1) >> sft >= 4096u) ++sft;
+    for (uint32_t i = tid; i < 4096; i += kSvgdThreads) sh.hist[i] = 0;
+    __syncthreads();
+    for (int64_t q = tid; q < n; q += kSvgdThreads) atomicAdd(&sh.hist[((uint32_t)key[q] - lo) >> sft], 1u);
+    __syncthreads();
+    uint32_t c[4], loc = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        c[b] = sh.hist[4 * tid + b];
+        loc += c[b];
+    }
+    const uint32_t excl = block_exclusive_scan(loc, sh);
+    uint32_t run = excl;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        if ((int64_t)run <= ra && ra < (int64_t)(run + c[b])) {
+            sh.bin = 4 * tid + b;
+            sh.before = run;
+        }
+        if ((int64_t)run <= rb && rb < (int64_t)(run + c[b])) {
+            sh.bin_b = 4 * tid + b;
+            sh.end_b = run + c[b];
+        }
+        run += c[b];
+    }
+    __syncthreads();
+    const uint32_t ba = sh.bin, bb = sh.bin_b, before = sh.before;
+    const uint32_t cnt = sh.end_b - before;
+    __syncthreads();
+    if (cnt > (uint32_t)kCandCap) {
+        bool got = false;
+        va = select_keyed(key, n, ra, rb != ra, K, rot, th, sh, &vb, &got);
+        if (rb == ra) {
+            vb = va;
+        } else if (!got) {
+            double unused;
+            vb = select_keyed(key, n, rb, false, K, rot, th, sh, &unused, &got);
+        }
+        return;
+    }
+    const uint32_t klo = lo + (ba << sft);
+    const uint32_t khi = min(hi, lo + ((bb + 1u) << sft) - 1u);
+    if (tid == 0) sh.ncand = 0;
+    __syncthreads();
+    // the pairs of the two bins, walking the triangle as the keys were
+    // written (wavefront per row k, lanes over l)
+    for (int k = wave; k < K; k += kSvgdWaves) {
+        const int64_t row = tri_row(k, K);
+        for (int l = k + 1 + lane; l < K; l += kWave) {
+            const uint32_t x = key[row + (l - k - 1)];
+            if (x >= klo && x <= khi) {
+                const uint32_t slot = atomicAdd(&sh.ncand, 1u);
+                if (slot < kCandCap)
+                    sh.cand[slot] = rot ? dist2_rot(th + 6 * k, th + 6 * l) : dist2_trans(th + 6 * k, th + 6 * l);
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t nc = min(sh.ncand, (uint32_t)kCandCap);
+    for (uint32_t i = tid; i < 2 * nc; i += kSvgdThreads) sh.hist[i] = 0;
+    __syncthreads();
+    // rank every candidate among all: candidate i and range g of the
+    // G = 1024 / nc ranges per thread
+    const uint32_t G = nc ? (uint32_t)kSvgdThreads / nc : 1u;
+    if ((uint32_t)tid < nc * G) {
+        const uint32_t i = tid % nc, g = tid / nc;
+        const uint32_t j0 = nc * g / G, j1 = nc * (g + 1) / G;
+        const double x = sh.cand[i];
+        uint32_t less = 0, leq = 0;
+#pragma unroll 8
+        for (uint32_t j = j0; j < j1; ++j) {
+            const double y = sh.cand[j];
+            less += y < x;
+            leq += y <= x;
+        }
+        if (less) atomicAdd(&sh.hist[i], less);
+        if (leq) atomicAdd(&sh.hist[nc + i], leq);
+    }
+    __syncthreads();
+    const int64_t qa = ra - before, qb = rb - before;
+    for (uint32_t t = tid; t < nc; t += kSvgdThreads) {
+        const double x = sh.cand[t];
+        const uint32_t less = sh.hist[t], leq = sh.hist[nc + t];
+        if ((int64_t)less <= qa && qa < (int64_t)leq) sh.dres = x;       // same value for all writers
+        if ((int64_t)less <= qb && qb < (int64_t)leq) sh.wmax[0] = x;
+    }
+    __syncthreads();
+    va = sh.dres;
+    vb = sh.wmax[0];
+    __syncthreads();
+}
+
 // Pair distances of the bandwidth kernel are kept as 16-bit keys in LDS up
 // to this many pairs (K up to about 345); beyond, as FP64 in global memory.
 constexpr int64_t kMaxKeyedPairs = 60000;
@@ -473,14 +605,7 @@ __device__ __forceinline__ void bandwidth_body(const SvgdArgs& a, int64_t p, int
                                                        : dist2_trans(th + 6 * k, th + 6 * l));
         }
         __syncthreads();
-        bool got = false;
-        va = select_keyed(key, np, ra, rb != ra, K, rot, th, sh, &vb, &got);
-        if (rb == ra) {
-            vb = va;
-        } else if (!got) {
-            double unused;
-            vb = select_keyed(key, np, rb, false, K, rot, th, sh, &unused, &got);
-        }
+        select_pair_keyed(key, np, ra, rb, K, rot, th, sh, va, vb);
     } else {
         double* d = a.dscr + (p * 2 + rot) * np;
         for (int k = tid >> 6; k < K; k += kSvgdWaves) {
