@@ -3,10 +3,10 @@
 //
 // One group of 512 threads per particle, two groups to a workgroup. Each
 // thread takes minibatch points i = t, t + 512, ...: it reduces the chunk
-// keys of its query and resolves the
-// winning tile to the matched reference index, recomputes the FP64
-// transform s' = R s + u, forms the
-// residual e = s' - r and the six contributions e and e^T (dR/dtheta_d) s,
+// keys of its query to the matched reference index (resolving the winning
+// tile of the FP32 search; the BF16 screen's keys carry the index),
+// recomputes the FP64 transform s' = R s + u, forms the residual
+// e = s' - r and the six contributions e and e^T (dR/dtheta_d) s,
 // accumulating in FP64. With the point-to-plane metric e is first replaced by
 // its projection rho n on the matched reference's unit normal n
 // (rho = n^T e), which gives rho n and rho n^T (dR/dtheta_d) s. The
@@ -32,7 +32,8 @@ struct GradArgs {
     int32_t* match;       // K*m per pair, pair-relative reference indices
     double* gbar;         // 6 per particle
     const double* nrm;    // point-to-plane: 4 doubles (n, 0) per packed reference; NULL: point-to-point
-    int32_t K, m, rows, pad_;
+    int32_t K, m, rows;
+    int32_t index_keys;   // 1: the keys carry the reference index (BF16 screen), 0: the tile
 };
 
 constexpr int kGradGroups = 2;   // particles per 1024-thread workgroup, kGradThreads threads each
@@ -61,7 +62,7 @@ __device__ __forceinline__ void grad_group(const GradArgs& a, int64_t pk, int64_
             const float4 s = a.src4[pd.src_off + a.sched[pd.sched_off + row * a.m + i]];
             const float4 qf = a.queries[pd.q_off + qi];
             const uint64_t key = min_chunk_keys(a.partial + pd.part_off + qi, pd.chunks, pd.part_stride);
-            const int32_t j = resolve_key(key, qf, a.ref4 + pd.ref_off, pd.n_ref_pad);
+            const int32_t j = key_index(key, a.index_keys != 0, qf, a.ref4 + pd.ref_off, pd.n_ref_pad);
             const float4 r = a.ref4[pd.ref_off + j];
             a.match[p * nq + qi] = j;
             double q[3];

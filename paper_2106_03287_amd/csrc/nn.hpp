@@ -155,15 +155,25 @@ __device__ __forceinline__ int32_t resolve_key(uint64_t key, float4 q, const flo
     return idx;
 }
 
+// Reference index of a reduced key: keyed by tile (the FP32 search), or by
+// the index itself (the BF16 screen, whose exact rerank knows it).
+__device__ __forceinline__ int32_t key_index(uint64_t key, bool by_index, float4 q, const float4* __restrict__ ref4,
+                                             int64_t n_ref_pad)
+{
+    if (!by_index) return resolve_key(key, q, ref4, n_ref_pad);
+    const int64_t j = (int64_t)(key & 0xffffffffull);
+    return (int32_t)(j < n_ref_pad ? j : 0);   // never out of range from the screen; keeps reads in bounds
+}
+
 // Reduce the per-chunk keys of directly given queries (standalone search).
 __global__ void nn_finish_kernel(const uint64_t* __restrict__ partial, const float4* __restrict__ queries,
                                  const float4* __restrict__ ref4, int64_t n_ref_pad, int64_t nq, int32_t chunks,
-                                 int32_t* __restrict__ idx, float* __restrict__ d2)
+                                 int32_t by_index, int32_t* __restrict__ idx, float* __restrict__ d2)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nq) return;
     const uint64_t k = min_chunk_keys(partial + i, chunks, nq);
-    idx[i] = resolve_key(k, queries[i], ref4, n_ref_pad);
+    idx[i] = key_index(k, by_index != 0, queries[i], ref4, n_ref_pad);
     if (d2) d2[i] = __uint_as_float((uint32_t)(k >> 32));
 }
 

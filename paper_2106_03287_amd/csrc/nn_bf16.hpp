@@ -22,9 +22,10 @@
 //
 // Rerank: each lane recomputes the exact FP32 distance (the same operation
 // sequence as the FP32 search) of its sixteen references in its best block,
-// keyed by their 16-reference tile; the two lanes of a query merge their
-// (distance, tile) keys. The key format is the FP32 search's, so chunk
-// reduction and tile resolution downstream are shared.
+// keyed by the reference index; the two lanes of a query merge their
+// (distance, index) keys. The FP32 search keys by 16-reference tile instead;
+// both order by distance, then lowest index, so the chunk reduction is
+// shared, and an index key needs no tile resolution downstream.
 //
 // Certificate: the result is the FP32 search's exact chunk minimum, ties
 // included. Let S be the screened and F the FP32 distance of a reference.
@@ -294,7 +295,7 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     }
 
     // exact FP32 rerank of the lane's sixteen references in its best block
-    // (keyed by their 16-reference tile), then the minimum over the two
+    // (keyed by the reference index), then the minimum over the two
     // lanes of each query
     const float4* __restrict__ rp = a.ref4 + pd.ref_off + c0;
     uint64_t key[G];
@@ -309,8 +310,7 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
             for (int t = 0; t < 16; ++t) {
                 const int row = blk_row(t, h);
                 const float4 rr = rp[rb + row];
-                k = min(k, pack_key(dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z),
-                                    (uint32_t)((c0 + rb + row) / kTile)));
+                k = min(k, pack_key(dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z), (uint32_t)(c0 + rb + row)));
             }
         }
         k = min(k, (uint64_t)__shfl_xor((unsigned long long)k, 32));
@@ -375,7 +375,7 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
                 for (int64_t e = lane; e < nref; e += kWave) {
                     const int64_t r = c0 + (t0 + e / 16) * kBlk + blk_row((int)(e & 15), fh);
                     const float4 rr = a.ref4[pd.ref_off + r];
-                    kb = min(kb, pack_key(dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z), (uint32_t)(r / kTile)));
+                    kb = min(kb, pack_key(dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z), (uint32_t)r));
                 }
 #pragma unroll
                 for (int o = kWave / 2; o > 0; o >>= 1) kb = min(kb, (uint64_t)__shfl_xor((unsigned long long)kb, o));

@@ -462,6 +462,7 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
     g.K = c->K;
     g.m = c->m;
     g.rows = c->rows;
+    g.index_keys = c->cfg.nn_mode == STEIN_ICP_NN_BF16_RERANK ? 1 : 0;
     const int32_t bw_pairs = const_bandwidth(c->cfg) ? 0 : c->P;
     const int64_t blocks = 2 * (int64_t)bw_pairs + ceil_div((int64_t)c->P * c->K, kGradGroups);
     hipLaunchKernelGGL(grad_bandwidth_kernel, dim3((unsigned)blocks), dim3(kSvgdThreads), grad_bw_lds_bytes(c->K), s,
@@ -1279,7 +1280,7 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
         }
         if (e == hipSuccess) {
             hipLaunchKernelGGL(nn_finish_kernel, grid1d(nq, 256), dim3(256), 0, s, a.partial, a.queries, a.ref4,
-                               pd.n_ref_pad, nq, pd.chunks, idx, d2);
+                               pd.n_ref_pad, nq, pd.chunks, bf16 ? 1 : 0, idx, d2);
             e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
