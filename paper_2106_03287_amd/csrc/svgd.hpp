@@ -449,30 +449,34 @@ __device__ inline double select_keyed(const uint16_t* key, int64_t n, int64_t r,
 // bins (adjacent ranks: nothing lies between them) are ranked by counting.
 // When those bins hold more than kCandCap pairs, select_keyed narrows each
 // rank on its own.
-__device__ inline void select_pair_keyed(const uint16_t* key, int64_t n, int64_t ra, int64_t rb, int K, int rot,
-                                         const double* th, SelectShared& sh, double& va, double& vb)
+// Before the barrier that publishes the keys: the wavefronts' key ranges,
+// a cleared histogram and reset selection fields (kmin / kmax: this
+// thread's keys).
+__device__ inline void select_pair_prologue(uint32_t kmin, uint32_t kmax, SelectShared& sh)
 {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid >> 6;
-    uint32_t kmin = 0xffffu, kmax = 0u;
-    for (int64_t q = tid; q < n; q += kSvgdThreads) {
-        const uint32_t x = key[q];
-        kmin = min(kmin, x);
-        kmax = max(kmax, x);
-    }
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
         kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, o));
         kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, o));
     }
     if (lane == 0) sh.wsum[wave] = kmin | (kmax << 16);
+    for (uint32_t i = tid; i < 4096; i += kSvgdThreads) sh.hist[i] = 0;
     if (tid == 0) {
         sh.bin = 0;
         sh.before = 0;
         sh.bin_b = 0;
         sh.end_b = 0;
+        sh.ncand = 0;
     }
-    __syncthreads();
+}
+
+__device__ inline void select_pair_keyed(const uint16_t* key, int64_t n, int64_t ra, int64_t rb, int K, int rot,
+                                         const double* th, SelectShared& sh, double& va, double& vb)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wave = tid >> 6;
     uint32_t lo = 0xffffu, hi = 0u;
     for (int w = 0; w < kSvgdWaves; ++w) {
         const uint32_t v = sh.wsum[w];
@@ -482,8 +486,6 @@ __device__ inline void select_pair_keyed(const uint16_t* key, int64_t n, int64_t
     const uint32_t range = hi - lo + 1;
     int sft = 0;
     while ((range - 1) >> sft >= 4096u) ++sft;
-    for (uint32_t i = tid; i < 4096; i += kSvgdThreads) sh.hist[i] = 0;
-    __syncthreads();
     for (int64_t q = tid; q < n; q += kSvgdThreads) atomicAdd(&sh.hist[((uint32_t)key[q] - lo) >> sft], 1u);
     __syncthreads();
     uint32_t c[4], loc = 0;
@@ -509,8 +511,8 @@ __device__ inline void select_pair_keyed(const uint16_t* key, int64_t n, int64_t
     __syncthreads();
     const uint32_t ba = sh.bin, bb = sh.bin_b, before = sh.before;
     const uint32_t cnt = sh.end_b - before;
-    __syncthreads();
     if (cnt > (uint32_t)kCandCap) {
+        __syncthreads();   // every thread has read the bins before select_keyed resets them
         bool got = false;
         va = select_keyed(key, n, ra, rb != ra, K, rot, th, sh, &vb, &got);
         if (rb == ra) {
@@ -523,8 +525,6 @@ __device__ inline void select_pair_keyed(const uint16_t* key, int64_t n, int64_t
     }
     const uint32_t klo = lo + (ba << sft);
     const uint32_t khi = min(hi, lo + ((bb + 1u) << sft) - 1u);
-    if (tid == 0) sh.ncand = 0;
-    __syncthreads();
     // the pairs of the two bins, walking the triangle as the keys were
     // written (wavefront per row k, lanes over l)
     for (int k = wave; k < K; k += kSvgdWaves) {
@@ -540,37 +540,51 @@ __device__ inline void select_pair_keyed(const uint16_t* key, int64_t n, int64_t
     }
     __syncthreads();
     const uint32_t nc = min(sh.ncand, (uint32_t)kCandCap);
-    for (uint32_t i = tid; i < 2 * nc; i += kSvgdThreads) sh.hist[i] = 0;
-    __syncthreads();
-    // rank every candidate among all: candidate i and range g of the
-    // G = 1024 / nc ranges per thread
-    const uint32_t G = nc ? (uint32_t)kSvgdThreads / nc : 1u;
-    if ((uint32_t)tid < nc * G) {
-        const uint32_t i = tid % nc, g = tid / nc;
-        const uint32_t j0 = nc * g / G, j1 = nc * (g + 1) / G;
-        const double x = sh.cand[i];
-        uint32_t less = 0, leq = 0;
-#pragma unroll 8
-        for (uint32_t j = j0; j < j1; ++j) {
-            const double y = sh.cand[j];
-            less += y < x;
-            leq += y <= x;
-        }
-        if (less) atomicAdd(&sh.hist[i], less);
-        if (leq) atomicAdd(&sh.hist[nc + i], leq);
-    }
-    __syncthreads();
     const int64_t qa = ra - before, qb = rb - before;
-    for (uint32_t t = tid; t < nc; t += kSvgdThreads) {
-        const double x = sh.cand[t];
-        const uint32_t less = sh.hist[t], leq = sh.hist[nc + t];
-        if ((int64_t)less <= qa && qa < (int64_t)leq) sh.dres = x;       // same value for all writers
-        if ((int64_t)less <= qb && qb < (int64_t)leq) sh.wmax[0] = x;
+    if (nc <= (uint32_t)kSvgdThreads / 4) {
+        // few candidates: each ranked by one thread against all
+        if ((uint32_t)tid < nc) {
+            const double x = sh.cand[tid];
+            uint32_t less = 0, leq = 0;
+            for (uint32_t j = 0; j < nc; ++j) {
+                const double y = sh.cand[j];
+                less += y < x;
+                leq += y <= x;
+            }
+            if ((int64_t)less <= qa && qa < (int64_t)leq) sh.dres = x;       // same value for all writers
+            if ((int64_t)less <= qb && qb < (int64_t)leq) sh.wmax[0] = x;
+        }
+    } else {
+        for (uint32_t i = tid; i < 2 * nc; i += kSvgdThreads) sh.hist[i] = 0;
+        __syncthreads();
+        // rank every candidate among all: candidate i and range g of the
+        // G = 1024 / nc ranges per thread
+        const uint32_t G = (uint32_t)kSvgdThreads / nc;
+        if ((uint32_t)tid < nc * G) {
+            const uint32_t i = tid % nc, g = tid / nc;
+            const uint32_t j0 = nc * g / G, j1 = nc * (g + 1) / G;
+            const double x = sh.cand[i];
+            uint32_t less = 0, leq = 0;
+#pragma unroll 8
+            for (uint32_t j = j0; j < j1; ++j) {
+                const double y = sh.cand[j];
+                less += y < x;
+                leq += y <= x;
+            }
+            if (less) atomicAdd(&sh.hist[i], less);
+            if (leq) atomicAdd(&sh.hist[nc + i], leq);
+        }
+        __syncthreads();
+        for (uint32_t t = tid; t < nc; t += kSvgdThreads) {
+            const double x = sh.cand[t];
+            const uint32_t less = sh.hist[t], leq = sh.hist[nc + t];
+            if ((int64_t)less <= qa && qa < (int64_t)leq) sh.dres = x;
+            if ((int64_t)less <= qb && qb < (int64_t)leq) sh.wmax[0] = x;
+        }
     }
     __syncthreads();
     va = sh.dres;
     vb = sh.wmax[0];
-    __syncthreads();
 }
 
 // Pair distances of the bandwidth kernel are kept as 16-bit keys in LDS up
@@ -598,12 +612,19 @@ __device__ __forceinline__ void bandwidth_body(const SvgdArgs& a, int64_t p, int
     double va, vb;
     if (np <= kMaxKeyedPairs) {
         uint16_t* key = reinterpret_cast<uint16_t*>(dyn + 6 * K);
+        // the keys, their range (per wavefront) and the cleared histogram
+        // of the selection, under one barrier
+        uint32_t kmin = 0xffffu, kmax = 0u;
         for (int k = tid >> 6; k < K; k += kSvgdWaves) {
             const int64_t row = tri_row(k, K);
-            for (int l = k + 1 + (tid & (kWave - 1)); l < K; l += kWave)
-                key[row + (l - k - 1)] = order_key(rot ? dist2_rot(th + 6 * k, th + 6 * l)
-                                                       : dist2_trans(th + 6 * k, th + 6 * l));
+            for (int l = k + 1 + (tid & (kWave - 1)); l < K; l += kWave) {
+                const uint16_t x = order_key(rot ? dist2_rot(th + 6 * k, th + 6 * l) : dist2_trans(th + 6 * k, th + 6 * l));
+                key[row + (l - k - 1)] = x;
+                kmin = min(kmin, (uint32_t)x);
+                kmax = max(kmax, (uint32_t)x);
+            }
         }
+        select_pair_prologue(kmin, kmax, sh);
         __syncthreads();
         select_pair_keyed(key, np, ra, rb, K, rot, th, sh, va, vb);
     } else {
