@@ -429,6 +429,26 @@ def test_bf16_screen_exact_ties_go_to_the_lowest_index():
     _bf16_check(q, ref)
 
 
+@pytest.mark.parametrize("seed", range(16))
+def test_bf16_screen_randomized_scales_offsets_and_near_ties(seed):
+    """The certificate's error bound scales with the centred norms, so the
+    screen is swept over cloud scales from 0.1 m to 100 m, centres up to
+    300 m from the origin, near-duplicate references (jittered copies) and
+    queries placed next to references (near-ties across blocks); indices and
+    distances equal the oracle's FP32 search bit for bit."""
+    rng = np.random.default_rng(900 + seed)
+    scale = 10.0 ** rng.uniform(-1, 2)
+    centre = rng.uniform(-1, 1, 3) * 10.0 ** rng.uniform(0, 2.5)
+    M = int(rng.integers(100, 20000))
+    nq = int(rng.integers(100, 4000))
+    ref = centre + rng.uniform(-scale, scale, (M, 3))
+    dup = rng.choice(M, M // 5, replace=False)
+    ref[dup[: len(dup) // 2]] = ref[dup[len(dup) // 2:2 * (len(dup) // 2)]] + rng.normal(0, 1e-6 * scale, (len(dup) // 2, 3))
+    near = rng.choice(M, nq, replace=True)
+    q = ref[near] + rng.normal(0, 1e-3 * scale, (nq, 3)) * rng.uniform(0, 1, (nq, 1))
+    _bf16_check(q.astype(np.float32), ref.astype(np.float32))
+
+
 def _grid_problem():
     """Cloud pair on an integer grid with repeated references: many exact
     ties between and inside the screen's 32-reference blocks."""
