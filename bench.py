@@ -24,23 +24,26 @@ sys.path.insert(0, ROOT)
 METRIC = "Stein-ICP iters/s & particle·point NN queries/s; time-to-MMD≤0.05 vs plain"
 VALU_PEAK_TFLOPS = 157.3    # MI355X FP32 vector peak: 256 CUs x 2.4 GHz x 256 FP32 flop/clk/CU
 MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
+HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E
 NORMAL_K = 10               # neighbours per normal of the point-to-plane metric
-FLOPS_PER_PAIR = 9          # 3 sub + 3 mul + 2 add (squared distance) + 1 compare
+# Algorithmic work of one pair evaluation of Eq. 1: the FP32 squared distance,
+# 3 subtractions, 1 multiply and 2 fused multiply-adds (2 flops each) = 8 flops.
+FLOPS_PER_PAIR = 8
+# Issued matrix-core work of the BF16 screen: two 32x32x16 BF16 products
+# (2 * 32 * 32 * 16 flops each) per 32 references x 32 queries = 64 flops per
+# pair (24 of the 32 K slots carry the three-part split, 8 are zero).
+MFMA_FLOPS_PER_PAIR_ISSUED = 64
 NN_SOURCES = ["paper_2106_03287_amd/csrc/nn.hpp", "paper_2106_03287_amd/csrc/common.hpp"]
 NN_BF16_SOURCES = NN_SOURCES + ["paper_2106_03287_amd/csrc/nn_bf16.hpp"]
 
 
 def host_info():
-    """Device, HIP and host CPU, and the GPU's clocks and power as found
-    (rocm-smi, run as a child process; any field it cannot give is None)."""
+    """Host CPU and the GPU's clocks and power as found (rocm-smi, run as a
+    child process). Called before this process touches the GPU: a process
+    that has initialised the GPU starts no other program. Any field that
+    cannot be read is None."""
     import subprocess
-    import torch
-    info = {"gpu": None, "hip": getattr(torch.version, "hip", None), "torch": torch.__version__,
-            "cpu_model": None, "cpu_threads": os.cpu_count(), "rocm_smi": None}
-    try:
-        info["gpu"] = torch.cuda.get_device_name(0)
-    except Exception:
-        pass
+    info = {"cpu_model": None, "cpu_threads": os.cpu_count(), "rocm_smi": None}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
@@ -60,6 +63,20 @@ def host_info():
     return info
 
 
+def gpu_info(host):
+    """The host record with the device, HIP and torch versions added (no
+    child process: the GPU is initialised by now)."""
+    import torch
+    info = dict(host)
+    info["hip"] = getattr(torch.version, "hip", None)
+    info["torch"] = torch.__version__
+    try:
+        info["gpu"] = torch.cuda.get_device_name(0)
+    except Exception:
+        info["gpu"] = None
+    return info
+
+
 def nn_source_sha(nn="fp32"):
     import hashlib
     h = hashlib.sha256()
@@ -68,18 +85,47 @@ def nn_source_sha(nn="fp32"):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, tiling, nn="fp32"):
-    """HBM bytes per NN launch from the committed counter runs, if they were
-    taken on the current kernel source, this workload, search mode and NN
-    shape; else None."""
+def measured_counters(workload, tiling, nn="fp32"):
+    """Counter figures of the NN kernel from the committed rocprofv3 runs
+    (HBM bytes per launch from FETCH_SIZE / WRITE_SIZE scaled by a plain
+    copy, and the matrix-core busy fraction), if they were taken on the
+    current kernel source, this workload, search mode and NN shape; else {}."""
     path = os.path.join(ROOT, "profiles", "nn_traffic.json")
     if not os.path.exists(path):
-        return None
+        return {}
     rec = json.load(open(path)).get(workload if nn == "fp32" else f"{workload}:{nn}")
     shape = "%d,%d,%d,%d" % (tiling["queries_per_lane"], tiling["waves"], tiling["chunk"], tiling["persist"])
     if not rec or rec.get("source_sha") != nn_source_sha(nn) or rec.get("tiling") != shape:
-        return None
-    return rec["hbm_bytes_per_launch"]
+        return {}
+    return rec
+
+
+def nn_roofline(nn, pairs_per_launch, nn_ms, counters):
+    """Roofline of the dominant kernel, the nearest-neighbour search: the
+    algorithmic 8 flops per pair evaluation over the launch time, against
+    the peak of the arithmetic the kernel runs on (BF16 matrix cores for the
+    screen, FP32 vector ALUs for the plain search); the screen's issued
+    matrix-core work, the counted HBM bytes and their rate beside it."""
+    t = nn_ms * 1e-3
+    useful = pairs_per_launch * FLOPS_PER_PAIR / t / 1e12
+    traffic = counters.get("hbm_bytes_per_launch")
+    out = {"achieved": round(useful, 3), "unit": "TFLOP/s", "traffic": traffic,
+           "flops_per_pair": FLOPS_PER_PAIR, "avg_launch_ms": round(nn_ms, 5),
+           "pair_evals_per_launch": pairs_per_launch,
+           "hbm_gbps": None if traffic is None else round(traffic / t / 1e9, 1),
+           "hbm_frac": None if traffic is None else round(traffic / t / 1e9 / HBM_PEAK_GBPS, 4)}
+    if nn == "bf16":
+        issued = pairs_per_launch * MFMA_FLOPS_PER_PAIR_ISSUED / t / 1e12
+        out.update(bound="mfma", peak=MFMA_BF16_PEAK_TFLOPS, frac=round(useful / MFMA_BF16_PEAK_TFLOPS, 4),
+                   kernel="nn_bf16_kernel",
+                   issued_mfma={"flops_per_pair": MFMA_FLOPS_PER_PAIR_ISSUED, "achieved": round(issued, 3),
+                                "frac": round(issued / MFMA_BF16_PEAK_TFLOPS, 4)},
+                   mfma_busy=counters.get("mfma_busy"))
+    else:
+        out.update(bound="alu", peak=VALU_PEAK_TFLOPS, frac=round(useful / VALU_PEAK_TFLOPS, 4),
+                   kernel="nn_fp32_kernel")
+    order = ["bound", "achieved", "peak", "unit", "frac", "traffic"]
+    return {k: out[k] for k in order + sorted(k for k in out if k not in order)}
 
 
 def cpu_baseline(prob, budget_s=15.0, plane=False):
@@ -103,7 +149,8 @@ def cpu_baseline(prob, budget_s=15.0, plane=False):
     return {"value": (n + 1) / (dt + per), "unit": "iters/s", "cores": cores, "kind": "oracle",
             "sample": f"iterations 2-{n + 2} of the {prob.name} workload (pair 0, K={prob.K}, "
                       f"m={prob.m}, M={len(prob.pair.ref)}{', point-to-plane' if plane else ''}), "
-                      f"FP64 oracle with OpenMP NN"}
+                      f"FP64 oracle with OpenMP NN; the rate of these iterations, extrapolated to "
+                      f"the T={prob.T} solve"}
 
 
 # NN shapes (queries per lane, wavefronts per workgroup, chunk, persistent
@@ -129,7 +176,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="kinect", choices=["cuboid", "kinect", "lidar", "batched", "proposal", "mc"])
+    ap.add_argument("--workload", default="lidar", choices=["cuboid", "kinect", "lidar", "batched", "proposal", "mc"])
     ap.add_argument("--runs", type=int, default=1000, help="independent single-particle runs of the mc workload")
     ap.add_argument("--pairs", type=int, default=64, help="pairs of the batched and proposal workloads")
     ap.add_argument("--workers", type=int, default=16,
@@ -154,6 +201,7 @@ def main():
               "(the particle-sharded multi-GPU design is described, not built)", file=sys.stderr)
         sys.exit(2)
 
+    args.host = host_info()   # before anything touches the GPU
     import torch
     import synth
     from paper_2106_03287_amd import stein_icp as S
@@ -236,24 +284,7 @@ def main():
     stage = sol.stage_times(prob.T)
     nn_ms = sol.time_nn(max(20, min(200, int(200 / max(stage["nn"] / prob.T, 1e-3)))))
     pairs_per_launch = prob.K * prob.m * M
-    achieved = pairs_per_launch * FLOPS_PER_PAIR / (nn_ms * 1e-3) / 1e12
-    if args.nn == "bf16":
-        # issued matrix-core work: one 16x16x32 BF16 MFMA (16384 flops) per
-        # 16 queries x 16 references, i.e. 64 flops per pair
-        mfma = pairs_per_launch * 64 / (nn_ms * 1e-3) / 1e12
-        roofline = {"bound": "mfma", "achieved": round(mfma, 3), "peak": MFMA_BF16_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(mfma / MFMA_BF16_PEAK_TFLOPS, 4),
-                    "traffic": measured_traffic(prob.name, tiling, "bf16"),
-                    "kernel": "nn_bf16_kernel", "avg_launch_ms": round(nn_ms, 5),
-                    "pair_evals_per_launch": pairs_per_launch,
-                    "alu_view": {"achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
-                                 "frac": round(achieved / VALU_PEAK_TFLOPS, 4)}}
-    else:
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
-                    "traffic": measured_traffic(prob.name, tiling),
-                    "kernel": "nn_fp32_kernel", "avg_launch_ms": round(nn_ms, 5),
-                    "pair_evals_per_launch": pairs_per_launch}
+    roofline = nn_roofline(args.nn, pairs_per_launch, nn_ms, measured_counters(prob.name, tiling, args.nn))
     mismatch, identical = None, None
     if args.nn == "bf16":
         # against the FP32 search from the same state: the first iteration's
@@ -304,7 +335,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, plane=args.metric == "plane")
-    out["host"] = host_info()
+    out["host"] = gpu_info(args.host)
     print(json.dumps(out), flush=True)
 
 
@@ -363,16 +394,7 @@ def run_batched(args):
     stage = batch.stage_times(T)
     nn_ms = batch.time_nn(20)
     pairs_per_launch = sum(K * m * len(p.pair.ref) for p in probs)
-    achieved = pairs_per_launch * FLOPS_PER_PAIR / (nn_ms * 1e-3) / 1e12
-    if args.nn == "bf16":
-        mfma = pairs_per_launch * 64 / (nn_ms * 1e-3) / 1e12
-        roofline = {"bound": "mfma", "achieved": round(mfma, 3), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(mfma / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None, "kernel": "nn_bf16_kernel",
-                    "avg_launch_ms": round(nn_ms, 5), "pair_evals_per_launch": pairs_per_launch}
-    else:
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None, "kernel": "nn_fp32_kernel",
-                    "avg_launch_ms": round(nn_ms, 5), "pair_evals_per_launch": pairs_per_launch}
+    roofline = nn_roofline(args.nn, pairs_per_launch, nn_ms, measured_counters("batched", tiling, args.nn))
     value = P * T / (ms_b / 1e3)
     out = {
         "metric": METRIC,
@@ -403,7 +425,9 @@ def run_batched(args):
     for s_ in singles:
         s_.close()
     batch.close()
-    out["host"] = host_info()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batched(probs, T)
+    out["host"] = gpu_info(args.host)
     print(json.dumps(out), flush=True)
 
 
@@ -481,16 +505,7 @@ def run_mc(args):
     tiling = mc.tiling()
     M = len(prob.pair.ref)
     pairs_per_launch = R * prob.m * M
-    if nn == "bf16":
-        mfma = pairs_per_launch * 64 / (nn_ms * 1e-3) / 1e12
-        roofline = {"bound": "mfma", "achieved": round(mfma, 3), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(mfma / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None, "kernel": "nn_bf16_kernel",
-                    "avg_launch_ms": round(nn_ms, 5), "pair_evals_per_launch": pairs_per_launch}
-    else:
-        achieved = pairs_per_launch * FLOPS_PER_PAIR / (nn_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None, "kernel": "nn_fp32_kernel",
-                    "avg_launch_ms": round(nn_ms, 5), "pair_evals_per_launch": pairs_per_launch}
+    roofline = nn_roofline(nn, pairs_per_launch, nn_ms, measured_counters("mc", tiling, nn))
     r4 = lambda v: [round(float(x), 4) for x in v]  # noqa: E731
     out = {
         "metric": METRIC,
@@ -526,8 +541,36 @@ def run_mc(args):
         out["cpu_baseline"] = cpu_baseline_mc(prob, T)
     mc.close()
     stein.close()
-    out["host"] = host_info()
+    out["host"] = gpu_info(args.host)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batched(probs, T, budget_s=15.0):
+    """The FP64 oracle on this host's cores over the batched workload's pairs
+    in order, one pair after another, each for the iterations that fit its
+    share of about ``budget_s`` seconds; pair-iterations per second over the
+    pairs it reached."""
+    import oracle
+    done, spent, names = 0, 0.0, []
+    for i, p in enumerate(probs):
+        cfg = oracle.make_config(p.K, p.m, len(p.pair.src), len(p.pair.ref), lr=p.lr)
+        st = oracle.State(p.theta0)
+        t0 = time.perf_counter()
+        oracle.run(cfg, p.pair.src, p.pair.ref, p.schedule, 1, st)
+        per = time.perf_counter() - t0
+        n = int(max(0, min(T - 1, (budget_s / 4 - per) / max(per, 1e-6))))
+        t0 = time.perf_counter()
+        if n:
+            oracle.run(cfg, p.pair.src, p.pair.ref, p.schedule, n, st)
+        spent += per + time.perf_counter() - t0
+        done += n + 1
+        names.append(f"pair {i} (M={len(p.pair.ref)}): {n + 1}")
+        if spent >= budget_s or i == 3:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": done / spent, "unit": "pair-iters/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 oracle with OpenMP NN, pairs one after another, iterations from the start: "
+                      + ", ".join(names)}
 
 
 def cpu_baseline_mc(prob, T, budget_s=15.0):
@@ -605,7 +648,7 @@ def run_proposal(args):
                      "flops_per_pair": 2 * PROPOSAL_MACS_PER_PAIR, "avg_ms_per_pair": round(net_ms / n, 5)},
     }
     model.close()
-    out["host"] = host_info()
+    out["host"] = gpu_info(args.host)
     print(json.dumps(out), flush=True)
 
 

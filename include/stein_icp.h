@@ -162,7 +162,8 @@ int stein_icp_get_state(const stein_icp_ctx *ctx, double *theta, double *mom, do
 
 /* Replace the optimiser state (device FP64 arrays as above; NULL moments are
  * set to zero) and the step count t >= 0, and recompute the rotations.
- * Asynchronous. */
+ * Blocking: the inputs are first checked for non-finite values
+ * (E_INVALID, context unchanged), then copied on `hip_stream`. */
 int stein_icp_set_state(stein_icp_ctx *ctx, const double *theta, const double *mom,
                         const double *vel, int64_t t, void *hip_stream);
 
@@ -188,6 +189,7 @@ int stein_icp_nn_tiling(const stein_icp_ctx *ctx, int32_t *queries_per_lane, int
 /* Force the nearest-neighbour work shape: queries_per_lane in {1, 2, 4},
  * waves in {4, 8, 16}, chunk a positive multiple of 32 references (capped
  * at each pair's padded reference count), persist in [0, 64] as above. The
+ * BF16 screen takes 1 or 2 queries per lane, and 4 or 8 waves with 2. The
  * shape changes only how the search is split over workgroups, never its
  * result. Blocking (reallocates the per-chunk key buffer and synchronises
  * `hip_stream`). */

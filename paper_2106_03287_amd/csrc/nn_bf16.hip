@@ -4,23 +4,25 @@
 
 namespace sicp {
 
-template <int Q>
-static void launch_q(int w, unsigned grid, const NNBf16Args& a, hipStream_t s)
+bool nn_bf16_shape_ok(int q, int w)
 {
-    switch (w) {
-    case 4: hipLaunchKernelGGL((nn_bf16_kernel<Q, 4>), dim3(grid), dim3(kWave * 4), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((nn_bf16_kernel<Q, 8>), dim3(grid), dim3(kWave * 8), 0, s, a); break;
-    default: hipLaunchKernelGGL((nn_bf16_kernel<Q, 16>), dim3(grid), dim3(kWave * 16), 0, s, a); break;
-    }
+    // two queries per lane need about 250 registers per lane: sixteen
+    // wavefronts (128 registers each) would spill, so that shape is not built
+    return (q == 1 && (w == 4 || w == 8 || w == 16)) || (q == 2 && (w == 4 || w == 8));
 }
 
 hipError_t launch_nn_bf16_kernel(int q, int w, unsigned grid, const NNBf16Args& a, hipStream_t s)
 {
-    if (w != 4 && w != 8 && w != 16) return hipErrorInvalidValue;
-    switch (q) {
-    case 1: launch_q<1>(w, grid, a, s); break;
-    case 2: launch_q<2>(w, grid, a, s); break;
-    default: return hipErrorInvalidValue;
+    if (!nn_bf16_shape_ok(q, w)) return hipErrorInvalidValue;
+    if (q == 1) {
+        switch (w) {
+        case 4: hipLaunchKernelGGL((nn_bf16_kernel<1, 4>), dim3(grid), dim3(kWave * 4), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((nn_bf16_kernel<1, 8>), dim3(grid), dim3(kWave * 8), 0, s, a); break;
+        default: hipLaunchKernelGGL((nn_bf16_kernel<1, 16>), dim3(grid), dim3(kWave * 16), 0, s, a); break;
+        }
+    } else {
+        if (w == 4) hipLaunchKernelGGL((nn_bf16_kernel<2, 4>), dim3(grid), dim3(kWave * 4), 0, s, a);
+        else hipLaunchKernelGGL((nn_bf16_kernel<2, 8>), dim3(grid), dim3(kWave * 8), 0, s, a);
     }
     return hipGetLastError();
 }

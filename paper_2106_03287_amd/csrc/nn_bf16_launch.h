@@ -19,8 +19,11 @@ struct NNBf16Args {
     int64_t nwork;
 };
 
-// q queries per lane (1 or 2), w wavefronts per workgroup (4, 8, 16), grid
-// workgroups (grid < nwork makes them persistent).
+// Shapes the screen is built for: q queries per lane (1 or 2) and w
+// wavefronts per workgroup (4, 8, 16 for one query per lane; 4, 8 for two).
+bool nn_bf16_shape_ok(int q, int w);
+
+// q, w as above, grid workgroups (grid < nwork makes them persistent).
 hipError_t launch_nn_bf16_kernel(int q, int w, unsigned grid, const NNBf16Args& a, hipStream_t s);
 
 // A fragments of the centred references of every pair; grid covers the

@@ -121,6 +121,19 @@ __global__ void copy_finite_kernel(const double* __restrict__ in, int64_t n, dou
     out[i] = v;
 }
 
+// Flag (bit 4) a non-finite FP64 value without copying it.
+__global__ void check_finite_kernel(const double* __restrict__ in, int64_t n, int* __restrict__ bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(in[i])) atomicOr(bad, 4);
+}
+
+__global__ void fill_i32_kernel(int* __restrict__ out, int64_t n, int v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v;
+}
+
 __global__ void fill_f64_kernel(double* __restrict__ out, int64_t n, double v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -594,7 +594,7 @@ int autotune(stein_icp_ctx* c, hipStream_t s)
     for (int q : {1, 2, 4})
         for (int w : {4, 8, 16})
             for (int64_t pw : {64, 128, 256, 512, 1024, 2048, 4096}) {
-                if (bf16 && q > 2) continue;
+                if (bf16 && !nn_bf16_shape_ok(q, w)) continue;
                 Tiling t;
                 t.q = q;
                 t.w = w;
@@ -1063,6 +1063,18 @@ int stein_icp_set_state(stein_icp_ctx* ctx, const double* theta, const double* m
     if (t < 0) return fail(STEIN_ICP_E_INVALID, "t must be >= 0");
     hipStream_t s = (hipStream_t)hip_stream;
     const int64_t n = (int64_t)ctx->P * ctx->K * 6;
+    // every input is checked before anything of the context changes
+    {
+        int bad = 0;
+        hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, ctx->flag, (int64_t)1, 0);
+        hipLaunchKernelGGL(check_finite_kernel, grid1d(n, 256), dim3(256), 0, s, theta, n, ctx->flag);
+        if (mom) hipLaunchKernelGGL(check_finite_kernel, grid1d(n, 256), dim3(256), 0, s, mom, n, ctx->flag);
+        if (vel) hipLaunchKernelGGL(check_finite_kernel, grid1d(n, 256), dim3(256), 0, s, vel, n, ctx->flag);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&bad, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (bad) return fail(STEIN_ICP_E_INVALID, "a particle or moment is non-finite");
+    }
     HIP_TRY(hipMemcpyAsync(ctx->theta, theta, 8 * n, hipMemcpyDeviceToDevice, s));
     if (mom) HIP_TRY(hipMemcpyAsync(ctx->mom, mom, 8 * n, hipMemcpyDeviceToDevice, s));
     else hipLaunchKernelGGL(fill_f64_kernel, grid1d(n, 256), dim3(256), 0, s, ctx->mom, n, 0.0);
@@ -1120,6 +1132,8 @@ int stein_icp_set_nn_tiling(stein_icp_ctx* ctx, int32_t qpl, int32_t waves, int3
     if (waves != 4 && waves != 8 && waves != 16) return fail(STEIN_ICP_E_INVALID, "waves must be 4, 8 or 16");
     if (chunk < kRefPad || chunk % kRefPad != 0)
         return fail(STEIN_ICP_E_INVALID, "chunk must be a positive multiple of 32");
+    if (ctx->cfg.nn_mode == STEIN_ICP_NN_BF16_RERANK && !nn_bf16_shape_ok(qpl, waves))
+        return fail(STEIN_ICP_E_INVALID, "the BF16 screen takes 1 or 2 queries per lane, and 4 or 8 waves with 2");
     Tiling t;
     t.q = qpl;
     t.w = waves;

@@ -294,6 +294,22 @@ def test_invalid_device_inputs_are_rejected():
     big[0, 0] = 3e9
     with pytest.raises(S.SteinICPError):
         S.stein_icp_nn(dev(prob.pair.src), dev(big))
+    # set_state checks every input before it changes anything
+    sol = S.SteinICP(gcfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule))
+    sol.step(1)
+    before = sol.get_state()
+    for which in range(3):
+        arrs = [dev(prob.theta0), torch.zeros(prob.K, 6, dtype=torch.float64, device="cuda"),
+                torch.zeros(prob.K, 6, dtype=torch.float64, device="cuda")]
+        arrs[which][1, 2] = float("nan")
+        with pytest.raises(S.SteinICPError) as e:
+            sol.set_state(*arrs, 0)
+        assert e.value.code == S.E_INVALID and "non-finite" in str(e.value)
+    after = sol.get_state()
+    for a, b in zip(before[:3], after[:3]):
+        assert torch.equal(a, b)
+    assert before[3] == after[3] == 1
+    sol.close()
 
 
 # ------------------------------------------------------------------ median selection paths
@@ -474,6 +490,18 @@ def test_bf16_screen_every_block_count_per_wavefront(q, w):
     prob = synth.make_problem("cuboid", 0, T=1)
     cases = [(prob.pair.src, prob.pair.ref, prob.theta0, prob.schedule, prob.K, prob.m, prob.schedule.shape[0]),
              _grid_problem()]
+    if (q, w) == (2, 16):
+        # not built (two queries per lane need more registers than sixteen
+        # wavefronts leave): the shape is refused, nothing is launched
+        cfg = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m, schedule_rows=1,
+                                         nn_mode=S.NN_BF16_RERANK)
+        sol = S.SteinICP(cfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule[:1]))
+        try:
+            with pytest.raises(S.SteinICPError):
+                sol.set_tiling(q, w, 64)
+        finally:
+            sol.close()
+        return
     for src, ref, theta0, sched, K, m, rows in cases:
         cfg = S.stein_icp_default_config(num_particles=K, batch_size=m, schedule_rows=rows, autotune=0,
                                          nn_mode=S.NN_BF16_RERANK)
