@@ -80,6 +80,23 @@ int stein_icp_proposal_param_count(int32_t num_particles, int64_t *count);
 int stein_icp_proposal_create(stein_icp_proposal **out, const stein_icp_proposal_config *cfg);
 int stein_icp_proposal_destroy(stein_icp_proposal *model);
 
+/* Weight file: the NumPy .npy format (magic "\x93NUMPY", version 1.0, 2.0 or
+ * 3.0, a little-endian header length, an ASCII dict header) holding one
+ * one-dimensional little-endian float32 array ('<f4', fortran_order False)
+ * of the parameter vector in the order above; its length, 172,928 + 1,542 K,
+ * fixes K (`np.save(path, params)` writes such a file).
+ * stein_icp_proposal_read_weights (host only) checks the file and reports
+ * *count values (may be NULL) for *num_particles = K (may be NULL); with
+ * params != NULL it also reads them into params (host, capacity values) and
+ * checks they are finite. E_INVALID for an unreadable or malformed file. */
+int stein_icp_proposal_read_weights(const char *path, float *params, int64_t capacity, int64_t *count,
+                                    int32_t *num_particles);
+
+/* Create a model (stein_icp_proposal_default_config, with the file's K) and
+ * load the parameters of a weight file into it. Blocking. On failure *out is
+ * NULL and nothing stays allocated. */
+int stein_icp_proposal_load(stein_icp_proposal **out, const char *weights_path);
+
 /* Copy `param_count` FP32 parameters in (resets the Adam moments and step
  * count) or out. Device pointers; enqueued on `hip_stream`. */
 int stein_icp_proposal_set_params(stein_icp_proposal *model, const float *params, void *hip_stream);

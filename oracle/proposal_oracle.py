@@ -20,17 +20,20 @@ set that Stein ICP otherwise draws uniformly, Sec. V):
   target set Y (K x 6 each) with a sum of Gaussian kernels over widths
   sigma_s (angle differences wrapped to [-pi, pi]); the batch loss is the
   mean over pairs.
-* backward: the chain rule through the above, written out per layer. Below
-  the max-pool it runs per (cloud, feature) slot on the winning point's row
-  (the same sum as the dense chain rule, since that part is linear once the
-  ReLU masks are fixed); the matrix products of the backward pass round their
-  operands like the forward ones when ``bf16=True``, the sum of scaled rows
-  that gives the last per-point layer's weight gradient does not.
+* backward: the dense chain rule through the above, layer by layer over
+  every point: the gradient of a pooled feature goes to the point that won
+  it (a scatter into an all-points gradient of the last per-point layer),
+  then back through each ReLU and matrix product. With ``bf16=True`` every
+  matrix product of the backward pass, like those of the forward pass,
+  rounds both of its operands to BF16 first; the bias gradients are plain
+  column sums.
 * Adam with bias correction.
 
 Pins (tests/test_proposal_oracle.py): BF16 rounding against torch's
 conversion; a hand-built network whose output has a closed form; gradients
-against central finite differences of the FP64 network; MMD^2 closed form at
+against central finite differences of the FP64 network; the BF16 gradients
+against torch autograd of the same network built from a matrix product that
+rounds its operands (forward and backward) to BF16; MMD^2 closed form at
 K = 1, zero on identical sets, positive otherwise, invariant under particle
 permutation and 2 pi angle shifts; Adam's first steps in closed form.
 """
@@ -195,26 +198,20 @@ def loss_and_grad(params, clouds, targets, K: int, sigma, bf16: bool = True):
     g["W4"] = matmul(c["F"].T, dZ, bf16)
     g["b4"] = dZ.sum(axis=0)
     dF = matmul(dZ, w["W4"].T, bf16)
-    # max-pool: the gradient of pooled feature f of cloud cl reaches only
-    # its winning point arg[cl, f]. Below the pool the backward is linear
-    # once the ReLU masks are fixed, so it is taken per (cloud, feature)
-    # slot: slot (cl, f) carries val = dF[cl, f] (F[cl, f] > 0) on feature f
-    # alone, and the rows of the layers below are those of the winner.
-    Fc = c["F"].reshape(B * 2, F3)
-    val = dF.reshape(B * 2, F3) * (Fc > 0)                      # (clouds, F3)
-    rows = (np.arange(B * 2)[:, None] * P + c["arg"]).reshape(-1)
-    G0, G1, G2 = c["x"][rows], c["H1"][rows], c["H2"][rows]      # slot rows
-    v = val.reshape(-1)
-    f_of = np.tile(np.arange(F3), B * 2)
-    # W3 / b3: dW3[k, f] = sum over clouds of val * h2(winner)[k] (a sum of
-    # scaled rows, not a matrix-core product: no BF16 rounding)
-    g["W3"] = np.einsum("cf,cfk->kf", val, G2.reshape(B * 2, F3, F2))
-    g["b3"] = val.sum(axis=0)
-    dA2 = v[:, None] * w["W3"].T[f_of] * (G2 > 0)               # (slots, F2)
-    g["W2"] = matmul(G1.T, dA2, bf16)
+    # max-pool: pooled feature f of cloud cl is the value of point arg[cl, f],
+    # so its gradient lands on that point's row of the last layer's output
+    npts = B * 2 * P
+    dH3 = np.zeros((npts, F3))
+    win = np.arange(B * 2)[:, None] * P + c["arg"]                 # (clouds, F3) point rows
+    dH3[win.reshape(-1), np.tile(np.arange(F3), B * 2)] = dF.reshape(B * 2, F3).reshape(-1)
+    dA3 = dH3 * (c["H3"] > 0)
+    g["W3"] = matmul(c["H2"].T, dA3, bf16)
+    g["b3"] = dA3.sum(axis=0)
+    dA2 = matmul(dA3, w["W3"].T, bf16) * (c["H2"] > 0)
+    g["W2"] = matmul(c["H1"].T, dA2, bf16)
     g["b2"] = dA2.sum(axis=0)
-    dA1 = matmul(dA2, w["W2"].T, bf16) * (G1 > 0)
-    g["W1"] = matmul(G0.T, dA1, bf16)
+    dA1 = matmul(dA2, w["W2"].T, bf16) * (c["H1"] > 0)
+    g["W1"] = matmul(c["x"].T, dA1, bf16)
     g["b1"] = dA1.sum(axis=0)
     return losses, pack(g, K), c
 

@@ -6,8 +6,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "stein_icp_proposal.h"
 
@@ -152,7 +154,7 @@ struct stein_icp_proposal {
     float *pool_v, *F, *Z, *Y, *dY, *dZ, *dF;
     int32_t *pool_i, *arg, *flags;
     unsigned long long* pool_keys;
-    float *G0, *G1, *G2, *val, *dA2, *dA1;   // per-slot rows of the sparse backward
+    float *G0, *G1, *G2, *dA3, *dA2, *dA1;   // winner rows of the sparse backward (F3 per cloud)
     float *ws, *colpart, *prep;
     int64_t ws_floats, colpart_floats;
     int64_t step = 0;
@@ -238,15 +240,16 @@ int forward(Model* m, hipStream_t s, const float* X, int64_t B)
 }
 
 // Backward pass of mean_b L_b from dY (already scaled by 1/B) into m->grad.
-// The head is dense; below the max-pool only the winning point of each
-// (cloud, feature) slot receives gradient, so the per-point layers are
-// differentiated on the 2 B F3 gathered slot rows instead of all 2 B P points.
+// The head is dense. Below the max-pool only the points that won a pooled
+// feature receive gradient: the per-point layers are differentiated on F3
+// rows per cloud (its distinct winners, then zero rows) instead of all P
+// points, with the dense chain rule's products (BF16 operands, FP32 sums).
 int backward(Model* m, hipStream_t s, const float* X, int64_t B)
 {
     const Layout L(m->K);
     const float* w = m->params;
     float* g = m->grad;
-    const int64_t K6 = 6 * m->K, slots = 2 * B * kF3;
+    const int64_t K6 = 6 * m->K, rows = 2 * B * kF3;
     // head: y = z W5 + b5, z = relu(f W4 + b4)
     CHECK(gemm(m, s, 1, 0, kFz, K6, B, m->Z, kFz, m->dY, K6, g + L.W5, K6, nullptr, 0));
     CHECK(colsum(m, s, m->dY, B, K6, g + L.b5));
@@ -255,25 +258,24 @@ int backward(Model* m, hipStream_t s, const float* X, int64_t B)
     CHECK(gemm(m, s, 1, 0, kFcat, kFz, B, m->F, kFcat, m->dZ, kFz, g + L.W4, kFz, nullptr, 0));
     CHECK(colsum(m, s, m->dZ, B, kFz, g + L.b4));
     CHECK(gemm(m, s, 0, 1, B, kFcat, kFz, m->dZ, kFz, w + L.W4, kFz, m->dF, kFcat, nullptr, 0));
-    // slots: gather the winning points' inputs and the pooled gradient, and
-    // recompute their first two layers with the forward's products (one K
-    // slice each, the same MFMA order, bias and ReLU: the same bits)
-    slot_gather_kernel<<<(unsigned)ceil_div(slots, 256), 256, 0, s>>>(X, m->arg, m->F, m->dF, kFcat, m->P, kF3, slots,
-                                                                      m->G0, m->val);
+    // winner rows: the winning points' inputs and the pooled gradients they
+    // carry; their first two layers are recomputed with the forward's
+    // products (one K slice each, the same MFMA order, bias and ReLU: the
+    // same bits)
+    winner_rows_kernel<kF3><<<(unsigned)(2 * B), kF3, 0, s>>>(X, m->arg, m->F, m->dF, kFcat, m->P, m->G0, m->dA3);
     HIP_TRY(hipGetLastError());
-    CHECK(launch_gemm(s, 0, 0, slots, kF1, 3, m->G0, 3, w + L.W1, kF1, m->G1, kF1, w + L.b1, 1, 0, 1, nullptr));
-    CHECK(launch_gemm(s, 0, 0, slots, kF2, kF1, m->G1, kF1, w + L.W2, kF2, m->G2, kF2, w + L.b2, 1, 0, 1, nullptr));
-    slot_w3_grad_kernel<<<(unsigned)ceil_div((int64_t)kF3 * (kF2 + 1), 256), 256, 0, s>>>(
-        m->G2, m->val, 2 * B, kF2, kF3, g + L.W3, g + L.b3);
-    slot_da2_kernel<<<(unsigned)ceil_div(slots * kF2, 256), 256, 0, s>>>(m->G2, m->val, w + L.W3, slots, kF2, kF3,
-                                                                        m->dA2);
-    HIP_TRY(hipGetLastError());
-    CHECK(gemm(m, s, 1, 0, kF1, kF2, slots, m->G1, kF1, m->dA2, kF2, g + L.W2, kF2, nullptr, 0));
-    CHECK(colsum(m, s, m->dA2, slots, kF2, g + L.b2));
-    CHECK(gemm(m, s, 0, 1, slots, kF1, kF2, m->dA2, kF2, w + L.W2, kF2, m->dA1, kF1, nullptr, 0));
-    relu_backward_kernel<<<(unsigned)ceil_div(slots * kF1, 256), 256, 0, s>>>(m->G1, m->dA1, slots * kF1);
-    CHECK(gemm(m, s, 1, 0, 3, kF1, slots, m->G0, 3, m->dA1, kF1, g + L.W1, kF1, nullptr, 0));
-    CHECK(colsum(m, s, m->dA1, slots, kF1, g + L.b1));
+    CHECK(launch_gemm(s, 0, 0, rows, kF1, 3, m->G0, 3, w + L.W1, kF1, m->G1, kF1, w + L.b1, 1, 0, 1, nullptr));
+    CHECK(launch_gemm(s, 0, 0, rows, kF2, kF1, m->G1, kF1, w + L.W2, kF2, m->G2, kF2, w + L.b2, 1, 0, 1, nullptr));
+    CHECK(gemm(m, s, 1, 0, kF2, kF3, rows, m->G2, kF2, m->dA3, kF3, g + L.W3, kF3, nullptr, 0));
+    CHECK(colsum(m, s, m->dA3, rows, kF3, g + L.b3));
+    CHECK(gemm(m, s, 0, 1, rows, kF2, kF3, m->dA3, kF3, w + L.W3, kF3, m->dA2, kF2, nullptr, 0));
+    relu_backward_kernel<<<(unsigned)ceil_div(rows * kF2, 256), 256, 0, s>>>(m->G2, m->dA2, rows * kF2);
+    CHECK(gemm(m, s, 1, 0, kF1, kF2, rows, m->G1, kF1, m->dA2, kF2, g + L.W2, kF2, nullptr, 0));
+    CHECK(colsum(m, s, m->dA2, rows, kF2, g + L.b2));
+    CHECK(gemm(m, s, 0, 1, rows, kF1, kF2, m->dA2, kF2, w + L.W2, kF2, m->dA1, kF1, nullptr, 0));
+    relu_backward_kernel<<<(unsigned)ceil_div(rows * kF1, 256), 256, 0, s>>>(m->G1, m->dA1, rows * kF1);
+    CHECK(gemm(m, s, 1, 0, 3, kF1, rows, m->G0, 3, m->dA1, kF1, g + L.W1, kF1, nullptr, 0));
+    CHECK(colsum(m, s, m->dA1, rows, kF1, g + L.b1));
     HIP_TRY(hipGetLastError());
     return STEIN_ICP_OK;
 }
@@ -360,7 +362,7 @@ int stein_icp_proposal_create(stein_icp_proposal** out, const stein_icp_proposal
     const size_t o_H3 = take(m->fused_pool ? 0 : 4 * rows * kF3);
     const size_t o_keys = take(8 * slots);
     const size_t o_G0 = take(4 * slots * 3), o_G1 = take(4 * slots * kF1), o_G2 = take(4 * slots * kF2);
-    const size_t o_val = take(4 * slots), o_dA2 = take(4 * slots * kF2), o_dA1 = take(4 * slots * kF1);
+    const size_t o_dA3 = take(4 * slots * kF3), o_dA2 = take(4 * slots * kF2), o_dA1 = take(4 * slots * kF1);
     const size_t o_pv = take(m->fused_pool ? 0 : 4 * 2 * m->Bmax * nch * kF3);
     const size_t o_pi = take(m->fused_pool ? 0 : 4 * 2 * m->Bmax * nch * kF3);
     const size_t o_arg = take(4 * 2 * m->Bmax * kF3);
@@ -387,7 +389,7 @@ int stein_icp_proposal_create(stein_icp_proposal** out, const stein_icp_proposal
     m->G0 = (float*)(a + o_G0);
     m->G1 = (float*)(a + o_G1);
     m->G2 = (float*)(a + o_G2);
-    m->val = (float*)(a + o_val);
+    m->dA3 = (float*)(a + o_dA3);
     m->dA2 = (float*)(a + o_dA2);
     m->dA1 = (float*)(a + o_dA1);
     m->pool_v = (float*)(a + o_pv);
@@ -439,6 +441,102 @@ int stein_icp_proposal_set_params(stein_icp_proposal* m, const float* params, vo
     HIP_TRY(hipMemsetAsync(m->adam_v, 0, 4 * m->n_params, s));
     m->step = 0;
     m->last_batch = 0;
+    return STEIN_ICP_OK;
+}
+
+int stein_icp_proposal_read_weights(const char* path, float* params, int64_t capacity, int64_t* count,
+                                    int32_t* num_particles)
+{
+    if (!path) return fail(STEIN_ICP_E_INVALID, "path is NULL");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(STEIN_ICP_E_INVALID, std::string("cannot open ") + path);
+    const auto bad = [&](const std::string& why) {
+        std::fclose(f);
+        return fail(STEIN_ICP_E_INVALID, std::string(path) + ": " + why);
+    };
+    // NumPy .npy: magic, version, little-endian header length (2 bytes in
+    // version 1, 4 in versions 2 and 3), an ASCII dict literal, the data
+    unsigned char pre[10];
+    if (std::fread(pre, 1, 8, f) != 8 || std::memcmp(pre, "\x93NUMPY", 6) != 0) return bad("not a .npy file");
+    const int major = pre[6];
+    uint32_t hlen = 0;
+    if (major == 1) {
+        if (std::fread(pre + 8, 1, 2, f) != 2) return bad("truncated header");
+        hlen = (uint32_t)pre[8] | ((uint32_t)pre[9] << 8);
+    } else if (major == 2 || major == 3) {
+        unsigned char b[4];
+        if (std::fread(b, 1, 4, f) != 4) return bad("truncated header");
+        hlen = (uint32_t)b[0] | ((uint32_t)b[1] << 8) | ((uint32_t)b[2] << 16) | ((uint32_t)b[3] << 24);
+    } else {
+        return bad("unsupported .npy version");
+    }
+    if (hlen > 65536) return bad("header too long");
+    std::string h(hlen, '\0');
+    if (std::fread(&h[0], 1, hlen, f) != hlen) return bad("truncated header");
+    const auto value_of = [&](const char* key) -> std::string {
+        const size_t k = h.find(key);
+        if (k == std::string::npos) return "";
+        size_t v = h.find(':', k);
+        if (v == std::string::npos) return "";
+        ++v;
+        while (v < h.size() && h[v] == ' ') ++v;
+        if (v >= h.size()) return "";
+        size_t e = v;
+        if (h[v] == '(') {
+            e = h.find(')', v);
+            if (e == std::string::npos) return "";
+            ++e;
+        } else {
+            while (e < h.size() && h[e] != ',' && h[e] != '}') ++e;
+        }
+        return h.substr(v, e - v);
+    };
+    if (value_of("'descr'") != "'<f4'") return bad("data must be little-endian float32 ('<f4')");
+    if (value_of("'fortran_order'") != "False") return bad("fortran_order must be False");
+    const std::string shp = value_of("'shape'");
+    long long n = -1;
+    char tail[8] = {0};
+    if (std::sscanf(shp.c_str(), "(%lld%7[,)]", &n, tail) != 2 || n < 1 || (std::strcmp(tail, ",)") != 0 &&
+                                                                              std::strcmp(tail, ")") != 0))
+        return bad("shape must be one-dimensional");
+    // the count fixes K: total = (fixed part) + 1542 K
+    const int64_t fixed = Layout(1).total - 6 * ((int64_t)kFz + 1);
+    const int64_t per_k = 6 * ((int64_t)kFz + 1);
+    if ((n - fixed) % per_k != 0 || (n - fixed) / per_k < 1 || (n - fixed) / per_k > STEIN_ICP_PROPOSAL_MAX_PARTICLES)
+        return bad("parameter count matches no particle count K in [1, 1024]");
+    const int32_t K = (int32_t)((n - fixed) / per_k);
+    if (count) *count = n;
+    if (num_particles) *num_particles = K;
+    if (params) {
+        if (capacity < n) return bad("params holds fewer than the file's values");
+        if (std::fread(params, 4, (size_t)n, f) != (size_t)n) return bad("truncated data");
+        for (long long i = 0; i < n; ++i)
+            if (!std::isfinite(params[i])) return bad("a parameter is not finite");
+    }
+    std::fclose(f);
+    return STEIN_ICP_OK;
+}
+
+int stein_icp_proposal_load(stein_icp_proposal** out, const char* path)
+{
+    if (!out) return fail(STEIN_ICP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int64_t n = 0;
+    int32_t K = 0;
+    CHECK(stein_icp_proposal_read_weights(path, nullptr, 0, &n, &K));
+    std::vector<float> host((size_t)n);
+    CHECK(stein_icp_proposal_read_weights(path, host.data(), n, &n, &K));
+    stein_icp_proposal_config cfg;
+    CHECK(stein_icp_proposal_default_config(&cfg));
+    cfg.num_particles = K;
+    stein_icp_proposal* m = nullptr;
+    CHECK(stein_icp_proposal_create(&m, &cfg));
+    if (hipMemcpy(m->params, host.data(), 4 * (size_t)n, hipMemcpyHostToDevice) != hipSuccess) {
+        const hipError_t e = hipGetLastError();
+        free_model(m);
+        return fail(STEIN_ICP_E_DEVICE, std::string("uploading the weights failed: ") + hipGetErrorString(e));
+    }
+    *out = m;
     return STEIN_ICP_OK;
 }
 

@@ -443,55 +443,60 @@ __global__ void pool_keys_finish_kernel(const unsigned long long* __restrict__ k
     arg[i] = (int32_t)(~(uint32_t)k);
 }
 
-// ------------------------------------------------------- sparse backward
-// The gradient of a max-pool reaches one point per (cloud c, feature f):
-// slot s = c F3 + f, point arg[s] of cloud c. Backward through the per-point
-// layers is linear once the ReLU masks are fixed, so it is taken slot by
-// slot: slot s carries the upstream gradient val_s = dF[c, f] (F[c, f] > 0)
-// on feature f only, and the rows of the layers below it are those of point
-// arg[s] (recomputed from the gathered input rows by the same products).
-// One thread per slot gathers the point's input and the slot's gradient.
-__global__ void slot_gather_kernel(const float* __restrict__ X, const int32_t* __restrict__ arg,
-                                   const float* __restrict__ F, const float* __restrict__ dF, int64_t ld_f, int64_t P,
-                                   int32_t F3, int64_t slots, float* __restrict__ G0, float* __restrict__ val)
+// Below the max-pool only the points that won a pooled feature receive
+// gradient. winner_rows_kernel gives each cloud F3 rows: its distinct
+// winning points first (in order of the first feature each wins), then zero
+// rows. Row u holds the point's input (G0) and the pooled gradients of the
+// features it wins (dA3[u][f] = dF[c][f] where F[c][f] > 0, else 0): the
+// dense backward's nonzero rows, so every product below is the dense chain
+// rule's product restricted to them (zero rows add exact zeros).
+// grid: clouds; F3 threads, one per feature.
+template <int F3>
+__global__ __launch_bounds__(F3) void winner_rows_kernel(const float* __restrict__ X, const int32_t* __restrict__ arg,
+                                                         const float* __restrict__ F, const float* __restrict__ dF,
+                                                         int64_t ld_f, int64_t P, float* __restrict__ G0,
+                                                         float* __restrict__ dA3)
 {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= slots) return;
-    const int64_t c = s / F3, f = s % F3;
-    const int64_t row = c * P + min(max(arg[s], 0), (int32_t)(P - 1));   // arg is in range; clamp anyway
-    G0[s * 3] = X[row * 3];
-    G0[s * 3 + 1] = X[row * 3 + 1];
-    G0[s * 3 + 2] = X[row * 3 + 2];
-    const int64_t e = (c / 2) * ld_f + (c % 2) * F3 + f;
-    val[s] = F[e] > 0.f ? dF[e] : 0.f;
-}
-
-// dW3[k][f] = sum_c val[c, f] G2[(c, f)][k] and db3[f] = sum_c val[c, f]
-// (FP32, clouds in order); thread (f, k), k == F2 computes the bias.
-__global__ void slot_w3_grad_kernel(const float* __restrict__ G2, const float* __restrict__ val, int64_t clouds,
-                                    int32_t F2, int32_t F3, float* __restrict__ dW3, float* __restrict__ db3)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)F3 * (F2 + 1)) return;
-    const int64_t f = i / (F2 + 1), k = i % (F2 + 1);
-    float sum = 0.f;
-    for (int64_t c = 0; c < clouds; ++c) {
-        const int64_t s = c * F3 + f;
-        sum += k < F2 ? val[s] * G2[s * F2 + k] : val[s];
+    constexpr int kW = 64;   // wavefront width
+    static_assert(F3 % kW == 0, "one thread per feature, whole wavefronts");
+    __shared__ int32_t pt[F3];
+    __shared__ int32_t row_of[F3];
+    __shared__ int32_t wtot[F3 / kW];
+    const int64_t c = blockIdx.x;
+    const int f = threadIdx.x, lane = f % kW, wv = f / kW;
+    const int32_t p = min(max(arg[c * F3 + f], 0), (int32_t)(P - 1));   // arg is in range; clamp anyway
+    pt[f] = p;
+    __syncthreads();
+    int first = f;   // first feature won by the same point
+    for (int j = 0; j < f; ++j)
+        if (pt[j] == p) {
+            first = j;
+            break;
+        }
+    const bool owner = first == f;
+    const unsigned long long ob = __ballot(owner);
+    const int before = __popcll(ob & ((1ull << lane) - 1ull));
+    if (lane == 0) wtot[wv] = __popcll(ob);
+    __syncthreads();
+    int r = before, rows = 0;
+    for (int w = 0; w < F3 / kW; ++w) {
+        r += w < wv ? wtot[w] : 0;
+        rows += wtot[w];
     }
-    if (k < F2) dW3[k * F3 + f] = sum;
-    else db3[f] = sum;
-}
-
-// dA2[s][k] = val_s W3[k][f_s] where G2[s][k] > 0, else 0.
-__global__ void slot_da2_kernel(const float* __restrict__ G2, const float* __restrict__ val,
-                                const float* __restrict__ W3, int64_t slots, int32_t F2, int32_t F3,
-                                float* __restrict__ dA2)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= slots * F2) return;
-    const int64_t s = i / F2, k = i % F2;
-    dA2[i] = G2[i] > 0.f ? val[s] * W3[k * F3 + s % F3] : 0.f;
+    if (owner) row_of[f] = r;
+    float* __restrict__ Dc = dA3 + c * F3 * F3;
+    for (int e = f; e < F3 * F3; e += F3) Dc[e] = 0.f;
+    float* __restrict__ Gc = G0 + c * F3 * 3;
+    if (owner) {
+        const float* x = X + (c * P + p) * 3;
+        Gc[3 * r] = x[0];
+        Gc[3 * r + 1] = x[1];
+        Gc[3 * r + 2] = x[2];
+    }
+    if (f >= rows) Gc[3 * f] = Gc[3 * f + 1] = Gc[3 * f + 2] = 0.f;
+    __syncthreads();   // the zeros and row_of before the scatter
+    const int64_t e = (c / 2) * ld_f + (c % 2) * F3 + f;
+    Dc[(int64_t)row_of[first] * F3 + f] = F[e] > 0.f ? dF[e] : 0.f;
 }
 
 // ------------------------------------------------------------ elementwise

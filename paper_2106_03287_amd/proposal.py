@@ -4,6 +4,7 @@ kernels. Tensors are torch CUDA (HIP) tensors; the library must be built."""
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -31,6 +32,7 @@ EXPORTS = [
     "stein_icp_proposal_destroy", "stein_icp_proposal_set_params", "stein_icp_proposal_get_params",
     "stein_icp_proposal_prepare", "stein_icp_proposal_forward", "stein_icp_proposal_loss",
     "stein_icp_proposal_adam", "stein_icp_proposal_mmd", "stein_icp_propose", "stein_icp_gemm_bf16",
+    "stein_icp_proposal_read_weights", "stein_icp_proposal_load",
 ]
 
 _ready = False
@@ -58,6 +60,8 @@ def lib():
     L.stein_icp_propose.argtypes = [vp, vp, i64, vp, i64, vp, C.POINTER(i32), vp]
     L.stein_icp_gemm_bf16.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i32, i32, i32,
                                       vp, vp]
+    L.stein_icp_proposal_read_weights.argtypes = [C.c_char_p, vp, i64, C.POINTER(i64), C.POINTER(i32)]
+    L.stein_icp_proposal_load.argtypes = [C.POINTER(vp), C.c_char_p]
     for name in EXPORTS:
         getattr(L, name).restype = C.c_int
     cfg = stein_icp_proposal_config()
@@ -163,6 +167,27 @@ def stein_icp_gemm_bf16(A, B, C_out, ta=0, tb=0, bias=None, relu=0, accumulate=0
         _ptr(bias), int(relu), int(accumulate), int(splits), _ptr(workspace), _stream(stream)))
 
 
+def stein_icp_proposal_read_weights(path):
+    """(parameters as a host float32 array, K) of a weight file, read and
+    checked by the library (no device needed)."""
+    n, K = C.c_int64(), C.c_int32()
+    b = os.fsencode(path)
+    _check("stein_icp_proposal_read_weights",
+           lib().stein_icp_proposal_read_weights(b, None, 0, C.byref(n), C.byref(K)))
+    out = np.empty(n.value, dtype=np.float32)
+    _check("stein_icp_proposal_read_weights",
+           lib().stein_icp_proposal_read_weights(b, out.ctypes.data, n.value, C.byref(n), C.byref(K)))
+    return out, K.value
+
+
+def stein_icp_proposal_load(path):
+    """A model created by the library from a weight file (default config with
+    the file's K)."""
+    m = C.c_void_p()
+    _check("stein_icp_proposal_load", lib().stein_icp_proposal_load(C.byref(m), os.fsencode(path)))
+    return m
+
+
 # ------------------------------------------------------------------ wrapper
 class Proposal:
     """A proposal model: forward, training steps and the one-pair proposal."""
@@ -177,6 +202,20 @@ class Proposal:
         if params is not None:
             self.set_params(params)
         self._torch = torch
+
+    @classmethod
+    def load(cls, path):
+        """The model the library loads from a weight file (default config,
+        K from the file)."""
+        import torch
+        self = cls.__new__(cls)
+        _, K = stein_icp_proposal_read_weights(path)
+        self.cfg = stein_icp_proposal_default_config(num_particles=K)
+        self.K, self.P = K, self.cfg.points
+        self.n_params = stein_icp_proposal_param_count(K)
+        self.model = stein_icp_proposal_load(path)
+        self._torch = torch
+        return self
 
     def set_params(self, params):
         import torch

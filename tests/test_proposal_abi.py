@@ -24,7 +24,7 @@ def _declared():
 def test_library_exports_every_declared_proposal_symbol():
     L = PR.lib()
     declared = _declared()
-    assert len(declared) == 13
+    assert len(declared) == 15
     for name in declared:
         assert hasattr(L, name), name
     assert sorted(PR.EXPORTS) == declared
@@ -100,3 +100,55 @@ def test_init_params_shape_and_scale():
     assert np.abs(blocks["W1"]).max() <= np.sqrt(6 / 3)
     assert np.abs(blocks["W5"]).max() <= 0.01 * np.sqrt(6 / 256)
     assert np.array_equal(p, PR.init_params(100, seed=3))
+
+
+# ------------------------------------------------------------------ weight files
+WEIGHTS = os.path.join(ROOT, "paper_2106_03287_amd", "weights", "proposal_k100_p4096.npy")
+
+
+def test_committed_weights_read_back_through_the_library():
+    got, K = PR.stein_icp_proposal_read_weights(WEIGHTS)
+    want = np.load(WEIGHTS, allow_pickle=False)
+    assert K == 100 and got.dtype == np.float32
+    assert np.array_equal(got, want)
+    assert len(got) == PO.param_count(100)
+
+
+@pytest.mark.parametrize("K", [1, 3, 1024])
+def test_weight_files_written_by_numpy_give_their_particle_count(tmp_path, K):
+    params = np.random.default_rng(K).standard_normal(PO.param_count(K)).astype(np.float32)
+    path = tmp_path / f"w{K}.npy"
+    np.save(path, params)
+    got, k = PR.stein_icp_proposal_read_weights(str(path))
+    assert k == K and np.array_equal(got, params)
+
+
+def _bad(tmp_path, name, data):
+    path = tmp_path / name
+    path.write_bytes(data)
+    with pytest.raises(S.SteinICPError) as e:
+        PR.stein_icp_proposal_read_weights(str(path))
+    assert e.value.code == S.E_INVALID
+    return str(e.value)
+
+
+def test_malformed_weight_files_are_rejected(tmp_path):
+    good = open(WEIGHTS, "rb").read()
+    assert "not a .npy" in _bad(tmp_path, "magic", b"XNUMPY" + good[6:])
+    assert "truncated" in _bad(tmp_path, "short", good[:-4])
+    f8 = tmp_path / "f8.npy"
+    np.save(f8, np.zeros(PO.param_count(2), dtype=np.float64))
+    assert "<f4" in _bad(tmp_path, "f8b.npy", f8.read_bytes())
+    m2 = tmp_path / "m2.npy"
+    np.save(m2, np.zeros((2, PO.param_count(2) // 2), dtype=np.float32))
+    assert "one-dimensional" in _bad(tmp_path, "m2b.npy", m2.read_bytes())
+    odd = tmp_path / "odd.npy"
+    np.save(odd, np.zeros(PO.param_count(2) + 1, dtype=np.float32))
+    assert "no particle count" in _bad(tmp_path, "oddb.npy", odd.read_bytes())
+    nan = np.zeros(PO.param_count(1), dtype=np.float32)
+    nan[5] = np.nan
+    nf = tmp_path / "nan.npy"
+    np.save(nf, nan)
+    assert "not finite" in _bad(tmp_path, "nanb.npy", nf.read_bytes())
+    with pytest.raises(S.SteinICPError):
+        PR.stein_icp_proposal_read_weights(str(tmp_path / "missing.npy"))

@@ -191,6 +191,76 @@ def test_network_gradient_matches_finite_differences():
         assert np.any(g[o:o + int(np.prod(s))] != 0), name
 
 
+class _RoundedMatmul(torch.autograd.Function):
+    """A @ B with both operands rounded to BF16 (through FP32), and the two
+    products of its backward rounding theirs the same way: the network's
+    stated precision, written with torch autograd as the chain rule."""
+
+    @staticmethod
+    def _r(t):
+        return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+    @staticmethod
+    def forward(ctx, A, B):
+        ctx.save_for_backward(A, B)
+        r = _RoundedMatmul._r
+        return r(A) @ r(B)
+
+    @staticmethod
+    def backward(ctx, G):
+        A, B = ctx.saved_tensors
+        r = _RoundedMatmul._r
+        return r(G) @ r(B).T, r(A).T @ r(G)
+
+
+def _torch_loss(params, clouds, targets, K, sig):
+    """The network and the mean biased MMD^2 in torch (FP64), every matrix
+    product through _RoundedMatmul."""
+    L = PO.layout(K)
+    p = torch.tensor(params, dtype=torch.float64, requires_grad=True)
+    w = {k: p[o:o + int(np.prod(s))].reshape(s) for k, (o, s) in L.items()}
+    mm = _RoundedMatmul.apply
+    X = torch.tensor(clouds, dtype=torch.float64)
+    B, _, P, _ = X.shape
+    h = X.reshape(-1, 3)
+    for i in (1, 2, 3):
+        h = torch.relu(mm(h, w[f"W{i}"]) + w[f"b{i}"])
+    pooled = h.reshape(B * 2, P, -1).max(dim=1).values.reshape(B, -1)
+    z = torch.relu(mm(pooled, w["W4"]) + w["b4"])
+    Y = (mm(z, w["W5"]) + w["b5"]).reshape(B, K, 6)
+    T = torch.tensor(targets, dtype=torch.float64)
+    sg = torch.tensor(np.atleast_2d(sig), dtype=torch.float64)
+
+    def k(U, V):
+        d = U[:, None, :] - V[None, :, :]
+        ang = d[..., 3:] - torch.round(d[..., 3:] / (2 * np.pi)) * (2 * np.pi)
+        d = torch.cat([d[..., :3], ang], dim=-1)
+        return sum(torch.exp(-0.5 * ((d / s) ** 2).sum(-1)) for s in sg)
+
+    loss = sum((k(Y[b], Y[b]).sum() + k(T[b], T[b]).sum() - 2 * k(Y[b], T[b]).sum()) / K ** 2
+               for b in range(B)) / B
+    loss.backward()
+    return float(loss.detach()), p.grad.numpy()
+
+
+@pytest.mark.parametrize("seed,P,B", [(21, 9, 2), (22, 33, 3), (23, 5, 1)])
+def test_bf16_gradient_equals_torch_autograd_of_the_rounded_network(seed, P, B):
+    """The BF16 backward (every matrix product rounding both operands, the
+    pooled gradient on the winning points) against torch autograd of the
+    same network: the chain rule is torch's, only the rounding rule is
+    shared."""
+    params, clouds, targets, K = _small_problem(seed=seed, K=3, P=P, B=B)
+    sig = np.array([[0.5] * 6, [2.0] * 6])
+    losses, g, cache = PO.loss_and_grad(params, clouds, targets, K, sig, bf16=True)
+    assert PO.pool_margin(cache) > 1e-6
+    tl, tg = _torch_loss(params, clouds, targets, K, sig)
+    assert np.mean(losses) == pytest.approx(tl, rel=1e-12)
+    np.testing.assert_allclose(g, tg, rtol=1e-9, atol=1e-12 * np.abs(tg).max())
+    # and it is not the FP64 network's gradient
+    _, g64, _ = PO.loss_and_grad(params, clouds, targets, K, sig, bf16=False)
+    assert not np.allclose(g, g64, rtol=1e-6)
+
+
 def test_bf16_gradient_stays_close_to_the_fp64_one():
     # one point per cloud: no max-pool decision that rounding could flip
     # (BF16 operands change individual terms by up to 2^-8 relative; sums
