@@ -211,6 +211,17 @@ int stein_icp_stage_times(stein_icp_ctx *ctx, int32_t n_iters, double *ms_out, v
  * Blocking. */
 int stein_icp_time_nn(stein_icp_ctx *ctx, int32_t n_launches, double *ms_per_launch, void *hip_stream);
 
+/* Certificate statistics of the BF16 screen (STEIN_ICP_NN_BF16_RERANK; both
+ * 0 for the FP32 search), accumulated since init over every nearest-
+ * neighbour launch of the context (iterations, profiled and timed launches):
+ * *certificates: screen certificates evaluated -- one per real query, chunk,
+ *   lane half (two) and wavefront holding blocks of the chunk (Eq. 1 is
+ *   proved exact for each);
+ * *rescans: those that failed and were searched again in FP32.
+ * Either output may be NULL. Blocking (synchronises `hip_stream`). */
+int stein_icp_nn_rescans(const stein_icp_ctx *ctx, int64_t *rescans, int64_t *certificates,
+                         void *hip_stream);
+
 /* Release the context and its device memory. NULL is a no-op. Blocking
  * (synchronises the device before freeing). */
 void stein_icp_destroy(stein_icp_ctx *ctx);

@@ -147,7 +147,6 @@ __global__ void pack_bf16_refs_kernel(const PairDesc* __restrict__ pairs, const 
     out[kWave] = __builtin_bit_cast(uint4, v1);
 }
 
-
 // A work item holds 64 Q queries (as in the FP32 search), taken as 2 Q groups
 // of 32 by every wavefront of the workgroup.
 template <int Q, int W>
@@ -365,6 +364,8 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
                 fail = !((double)sec[g] - margin > (double)fwg * (1.0 + 8.0 * u));
             }
             unsigned long long mask = __ballot(fail);
+            if (mask != 0ull && a.rescans != nullptr && lane == 0)
+                atomicAdd(a.rescans, (unsigned long long)__popcll(mask));
             while (mask != 0ull) {   // wave-uniform
                 const int b = __ffsll((long long)mask) - 1;
                 mask &= mask - 1ull;

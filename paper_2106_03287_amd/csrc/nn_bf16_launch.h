@@ -17,6 +17,7 @@ struct NNBf16Args {
     const float4* queries;
     uint64_t* partial;
     int64_t nwork;
+    unsigned long long* rescans;   // if set: certificates that failed, accumulated
 };
 
 // Shapes the screen is built for: q queries per lane (1 or 2) and w

@@ -119,18 +119,25 @@ struct Tiling {
 
 // Default shape: enough workgroups to give every SIMD several waves, with at
 // least 64 references (4 tiles) per wave; the autotuner refines it.
+int default_queries_per_lane(int64_t nq) { return nq >= 65536 ? 4 : (nq >= 8192 ? 2 : 1); }
+
+// References per chunk for a pair of n_ref_pad references when `pairs` pairs
+// of nq queries each (q per lane) share the launch.
+int32_t default_chunk(int64_t n_ref_pad, int64_t nq, int q, int64_t pairs)
+{
+    const int64_t qb = ceil_div(nq, (int64_t)kWave * q);
+    const int64_t target_wg = 4096;  // x4 waves = 16k waves over 1024 SIMDs
+    const int64_t per_pair = std::max<int64_t>(1, ceil_div(target_wg, pairs * qb));
+    const int64_t max_chunks = std::max<int64_t>(1, n_ref_pad / (4 * 64));
+    const int64_t c = std::min(per_pair, max_chunks);
+    return (int32_t)round_up(ceil_div(n_ref_pad, c), 4 * kTile);
+}
+
 Tiling default_tiling(const std::vector<PairDesc>& pd, int64_t nq)
 {
     Tiling t;
-    t.q = nq >= 65536 ? 4 : (nq >= 8192 ? 2 : 1);
-    const int64_t qb = ceil_div(nq, (int64_t)kWave * t.q);
-    const int64_t target_wg = 4096;  // x4 waves = 16k waves over 1024 SIMDs
-    const int64_t per_pair = std::max<int64_t>(1, ceil_div(target_wg, (int64_t)pd.size() * qb));
-    for (const auto& p : pd) {
-        const int64_t max_chunks = std::max<int64_t>(1, p.n_ref_pad / (4 * 64));
-        const int64_t c = std::min(per_pair, max_chunks);
-        t.chunk.push_back((int32_t)round_up(ceil_div(p.n_ref_pad, c), 4 * kTile));
-    }
+    t.q = default_queries_per_lane(nq);
+    for (const auto& p : pd) t.chunk.push_back(default_chunk(p.n_ref_pad, nq, t.q, (int64_t)pd.size()));
     return t;
 }
 
@@ -180,6 +187,8 @@ struct stein_icp_ctx {
     double* nrm = nullptr;       // point-to-plane: (n, 0) per packed reference, FP64
     double* dscr = nullptr;
     int* flag = nullptr;
+    unsigned long long* rescans = nullptr;   // failed screen certificates (BF16 search), accumulated
+    int64_t certificates = 0;                // screen certificates enqueued so far (host count)
 
     WorkItem* d_work = nullptr;  // separate allocations: resized by the tuner
     uint64_t* partial = nullptr;
@@ -356,6 +365,22 @@ void build_work(stein_icp_ctx* c)
     }
 }
 
+// Screen certificates one NN launch evaluates: every real query, for every
+// chunk, once per lane half (two) and per wavefront that holds blocks of the
+// chunk (min(waves, blocks)).
+int64_t certificates_per_launch(const stein_icp_ctx* c)
+{
+    if (c->cfg.nn_mode != STEIN_ICP_NN_BF16_RERANK) return 0;
+    int64_t n = 0;
+    for (const auto& g : c->groups)
+        for (int32_t ch = 0; ch < g.chunks; ++ch) {
+            const int64_t blocks = (std::min<int64_t>((int64_t)(ch + 1) * g.chunk, g.n_ref_pad) -
+                                    (int64_t)ch * g.chunk) / kRefPad;
+            n += g.nq * 2 * std::min<int64_t>(c->tiling.w, blocks);
+        }
+    return n;
+}
+
 int64_t partial_elems(const stein_icp_ctx* c)
 {
     int64_t n = 0;
@@ -442,6 +467,7 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
             b.apack = c->apack;
             b.queries = c->queries;
             b.partial = c->partial;
+            b.rescans = c->rescans;
             return launch_nn_bf16(c->tiling, (unsigned)c->work.size(), b, s);
         }
         return launch_nn(c->tiling, (unsigned)c->work.size(), nn_args(c), s);
@@ -546,6 +572,7 @@ int run_iters(stein_icp_ctx* c, int32_t n, hipStream_t s)
 {
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(s, &st));
+    c->certificates += (int64_t)n * certificates_per_launch(c);
     if (!c->cfg.use_graph || st != hipStreamCaptureStatusNone) {
         for (int32_t i = 0; i < n; ++i) {
             HIP_TRY(enqueue_iteration(c, s));
@@ -655,7 +682,12 @@ int autotune(stein_icp_ctx* c, hipStream_t s)
     c->tiling = best_t;
     c->tuned_ms = best;
     g_tuned[tk] = {best_t, best};
-    return upload_tiling(c, s);
+    const int rc = upload_tiling(c, s);
+    if (rc) return rc;
+    // the tuner's trial launches are not counted
+    HIP_TRY(hipMemsetAsync(c->rescans, 0, sizeof(unsigned long long), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return STEIN_ICP_OK;
 }
 
 // The k nearest of n_ref references for nq queries (device float4 arrays)
@@ -844,6 +876,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     const size_t o_nrm = take(plane ? 32 * (size_t)ro : 32);
     const size_t o_dscr = take(8 * (size_t)P * npairs2);
     const size_t o_flag = take(64);
+    const size_t o_rescans = take(64);
     if (hipMalloc(&c->arena, off) != hipSuccess) {
         (void)hipGetLastError();
         delete c;
@@ -871,6 +904,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
     c->nrm = (double*)(c->arena + o_nrm);
     c->dscr = (double*)(c->arena + o_dscr);
     c->flag = (int*)(c->arena + o_flag);
+    c->rescans = (unsigned long long*)(c->arena + o_rescans);
 
     auto bail = [&](int code) {
         free_ctx(c);
@@ -1167,7 +1201,10 @@ int stein_icp_stage_times(stein_icp_ctx* ctx, int32_t n_iters, double* ms_out, v
             if (err == hipSuccess) err = hipEventRecord(e[st + 1], s);
         }
         if (err != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, std::string("profiled step: ") + hipGetErrorString(err));
-        else advance(ctx, 1);
+        else {
+            advance(ctx, 1);
+            ctx->certificates += certificates_per_launch(ctx);
+        }
     }
     if (rc == STEIN_ICP_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, "sync failed");
     double t[kStages] = {0, 0, 0};
@@ -1196,6 +1233,7 @@ int stein_icp_time_nn(stein_icp_ctx* ctx, int32_t n_launches, double* ms_per_lau
     hipError_t e = enqueue_stage(ctx, 0, s);  // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, s);
     for (int32_t i = 0; i < n_launches && e == hipSuccess; ++i) e = enqueue_stage(ctx, 0, s);
+    ctx->certificates += (int64_t)(n_launches + 1) * certificates_per_launch(ctx);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -1204,6 +1242,18 @@ int stein_icp_time_nn(stein_icp_ctx* ctx, int32_t n_launches, double* ms_per_lau
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return fail(STEIN_ICP_E_DEVICE, std::string("stein_icp_time_nn: ") + hipGetErrorString(e));
     *ms_per_launch = (double)ms / n_launches;
+    return STEIN_ICP_OK;
+}
+
+int stein_icp_nn_rescans(const stein_icp_ctx* ctx, int64_t* rescans, int64_t* certificates, void* hip_stream)
+{
+    if (!ctx) return fail(STEIN_ICP_E_INVALID, "ctx is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    unsigned long long n = 0;
+    HIP_TRY(hipMemcpyAsync(&n, ctx->rescans, sizeof(n), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (rescans) *rescans = (int64_t)n;
+    if (certificates) *certificates = ctx->certificates;
     return STEIN_ICP_OK;
 }
 

@@ -61,7 +61,7 @@ EXPORTS = [
     "stein_icp_default_config", "stein_icp_init", "stein_icp_batch_init", "stein_icp_step",
     "stein_icp_particles", "stein_icp_get_state", "stein_icp_set_state",
     "stein_icp_get_diagnostics", "stein_icp_shape", "stein_icp_nn_tiling", "stein_icp_set_nn_tiling",
-    "stein_icp_stage_times", "stein_icp_time_nn",
+    "stein_icp_stage_times", "stein_icp_time_nn", "stein_icp_nn_rescans",
     "stein_icp_destroy",
     "stein_icp_last_error", "stein_icp_nn", "stein_icp_make_schedule", "stein_icp_make_init",
     "stein_icp_knn", "stein_icp_normals", "stein_icp_get_normals", "stein_icp_posterior_scores",
@@ -97,6 +97,7 @@ def lib():
     L.stein_icp_set_nn_tiling.argtypes = [vp, i32, i32, i32, i32, vp]
     L.stein_icp_stage_times.argtypes = [vp, i32, C.POINTER(dbl), vp]
     L.stein_icp_time_nn.argtypes = [vp, i32, C.POINTER(dbl), vp]
+    L.stein_icp_nn_rescans.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), vp]
     L.stein_icp_destroy.argtypes = [vp]
     L.stein_icp_destroy.restype = None
     L.stein_icp_last_error.argtypes = []
@@ -297,6 +298,13 @@ def stein_icp_time_nn(ctx, n_launches, stream=None):
     return ms.value
 
 
+def stein_icp_nn_rescans(ctx, stream=None):
+    """(failed certificates, certificates) of the BF16 screen since init."""
+    r, n = C.c_int64(), C.c_int64()
+    _check("stein_icp_nn_rescans", lib().stein_icp_nn_rescans(ctx, C.byref(r), C.byref(n), _stream(stream)))
+    return r.value, n.value
+
+
 def stein_icp_destroy(ctx):
     if ctx:
         lib().stein_icp_destroy(ctx)
@@ -417,6 +425,9 @@ class SteinICP:
 
     def time_nn(self, n_launches):
         return stein_icp_time_nn(self.ctx, n_launches)
+
+    def nn_rescans(self):
+        return stein_icp_nn_rescans(self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):
