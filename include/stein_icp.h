@@ -237,6 +237,22 @@ const char *stein_icp_last_error(void);
 int stein_icp_nn(const float *q_xyz, int64_t nq, const float *ref_xyz, int64_t n_ref,
                  int32_t mode, int32_t *idx, float *d2, void *hip_stream);
 
+/* stein_icp_nn for callers that cannot allocate device memory (code that
+ * runs while a stream is being captured into a hipGraph, tight serving
+ * loops, harnesses that forbid hipMalloc): the same search, arguments,
+ * validation, answers (bit for bit) and blocking behaviour, with no call to
+ * hipMalloc or hipFree. Its working memory -- packed queries (16 B each),
+ * packed references (16 B per reference padded to a multiple of 32, plus
+ * 64 B of BF16 fragments for BF16_RERANK), the work table and the per-chunk
+ * keys (8 B per query and reference chunk; fewer chunks are used when they
+ * would not fit) -- lives in a 32 MiB array inside the library, one per GPU,
+ * held until the process ends. E_INVALID when a search needs more than that
+ * (FP32: beyond about 1.2 M queries against 0.1 M references). Every call on
+ * one GPU uses that GPU's array: calls that overlap on one GPU (other
+ * threads or streams) race and must be serialised by the caller. */
+int stein_icp_nn_noalloc(const float *q_xyz, int64_t nq, const float *ref_xyz, int64_t n_ref,
+                         int32_t mode, int32_t *idx, float *d2, void *hip_stream);
+
 /* Standalone k-nearest-neighbour search under Eq. 1's metric: for each
  * query the k smallest (FP32 squared distance, index) pairs in ascending
  * order, ties to the lower index (the neighbourhoods of the normals).

@@ -27,6 +27,12 @@ hipError_t launch_nn_bf16_kernel(int q, int w, unsigned grid, const NNBf16Args& 
     return hipGetLastError();
 }
 
+hipError_t launch_bf16_centre(PairDesc* pair, const float4* ref4, int64_t n_ref, hipStream_t s)
+{
+    hipLaunchKernelGGL(bf16_centre_kernel, dim3(1), dim3(kCentreThreads), 0, s, pair, ref4, n_ref);
+    return hipGetLastError();
+}
+
 hipError_t launch_pack_bf16(const PairDesc* pairs, int32_t n_pairs, int64_t max_blocks, const float4* ref4,
                             uint4* apack, hipStream_t s)
 {

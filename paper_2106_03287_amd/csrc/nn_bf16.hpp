@@ -147,6 +147,69 @@ __global__ void pack_bf16_refs_kernel(const PairDesc* __restrict__ pairs, const 
     out[kWave] = __builtin_bit_cast(uint4, v1);
 }
 
+// Centre of the screen found on the device, for callers that hand the
+// library no host copy of the cloud: c0[0..2] = the centroid of the n
+// references (FP64 sums in a fixed order, rounded to FP32) and c0[3] an upper
+// bound of the centred norms as the screen forms them (FP32 differences,
+// FP64 norms), raised by 2^-20 relative and one FP32 step. The screen's
+// answer does not depend on c0 (it is certified); its error bound needs
+// c0[3] to bound every centred norm. One workgroup of kCentreThreads.
+constexpr int kCentreThreads = 1024;
+__global__ __launch_bounds__(kCentreThreads) void bf16_centre_kernel(PairDesc* __restrict__ pd,
+                                                                     const float4* __restrict__ ref4, int64_t n)
+{
+    constexpr int WV = kCentreThreads / kWave;
+    __shared__ double red[WV][3];
+    __shared__ float c0s[3];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = tid; i < n; i += kCentreThreads) {
+        const float4 r = ref4[i];
+        acc[0] += r.x;
+        acc[1] += r.y;
+        acc[2] += r.z;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) acc[d] += __shfl_xor(acc[d], o);
+        if (lane == 0) red[wv][d] = acc[d];
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double sum = 0.0;
+        for (int w = 0; w < WV; ++w) sum += red[w][tid];
+        const double mean = sum / (double)n;
+        c0s[tid] = isfinite(mean) ? (float)mean : 0.0f;
+    }
+    __syncthreads();
+    const float cx = c0s[0], cy = c0s[1], cz = c0s[2];
+    double r2 = 0.0;
+    for (int64_t i = tid; i < n; i += kCentreThreads) {
+        const float4 r = ref4[i];
+        float dx, dy, dz;
+        {
+#pragma clang fp contract(off)
+            dx = r.x - cx;
+            dy = r.y - cy;
+            dz = r.z - cz;
+        }
+        r2 = fmax(r2, ((double)dx * dx + (double)dy * dy) + (double)dz * dz);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) r2 = fmax(r2, __shfl_xor(r2, o));
+    if (lane == 0) red[wv][0] = r2;
+    __syncthreads();
+    if (tid == 0) {
+        double m = 0.0;
+        for (int w = 0; w < WV; ++w) m = fmax(m, red[w][0]);
+        pd->c0[0] = cx;
+        pd->c0[1] = cy;
+        pd->c0[2] = cz;
+        pd->c0[3] = nextafterf((float)(sqrt(m) * (1.0 + 0x1.0p-20)), __builtin_inff());
+    }
+}
+
 // A work item holds 64 Q queries (as in the FP32 search), taken as 2 Q groups
 // of 32 by every wavefront of the workgroup.
 template <int Q, int W>

@@ -27,6 +27,10 @@ bool nn_bf16_shape_ok(int q, int w);
 // q, w as above, grid workgroups (grid < nwork makes them persistent).
 hipError_t launch_nn_bf16_kernel(int q, int w, unsigned grid, const NNBf16Args& a, hipStream_t s);
 
+// The screen's centre c0 of one pair from its n_ref packed references, on
+// the device (written into pair->c0).
+hipError_t launch_bf16_centre(PairDesc* pair, const float4* ref4, int64_t n_ref, hipStream_t s);
+
 // A fragments of the centred references of every pair; grid covers the
 // largest pair's 16-reference blocks.
 hipError_t launch_pack_bf16(const PairDesc* pairs, int32_t n_pairs, int64_t max_blocks, const float4* ref4,

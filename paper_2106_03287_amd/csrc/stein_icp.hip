@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <string>
 #include <vector>
@@ -1352,6 +1353,151 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     if (e != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, std::string("stein_icp_nn: ") + hipGetErrorString(e));
     (void)hipFree(mem);
     return rc;
+}
+
+namespace {
+
+// Scratch of stein_icp_nn_noalloc: device memory of this library's code
+// object, one copy on every GPU the library runs on, held until the process
+// ends. Host code addresses it only through the pointer hipGetSymbolAddress
+// returns for the current device (the array's name is not a device address
+// on the host).
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// The scratch array's device address on the current device, looked up once
+// per device.
+int scratch_on_device(char** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(STEIN_ICP_E_DEVICE, "device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(STEIN_ICP_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch[dev] = (char*)p;
+    }
+    *out = g_scratch[dev];
+    return STEIN_ICP_OK;
+}
+
+// Pair descriptor, cleared flag and work table (query block, chunk) of a
+// standalone search, written on the device.
+__global__ void nn_setup_kernel(PairDesc pd, PairDesc* __restrict__ pd_out, WorkItem* __restrict__ work,
+                                int64_t nwork, int32_t chunks, int* __restrict__ flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        *pd_out = pd;
+        *flag = 0;
+    }
+    if (i < nwork) work[i] = WorkItem{0, (int32_t)(i / chunks), (int32_t)(i % chunks), 0};
+}
+
+}  // namespace
+
+int stein_icp_nn_noalloc(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n_ref, int32_t mode,
+                         int32_t* idx, float* d2, void* hip_stream)
+{
+    if (nq < 0 || n_ref < 1) return fail(STEIN_ICP_E_INVALID, "need nq >= 0 and n_ref >= 1");
+    if (nq > kMaxRef || n_ref > kMaxRef) return fail(STEIN_ICP_E_INVALID, "sizes must be below 2^31 - 64");
+    if (mode != STEIN_ICP_NN_FP32 && mode != STEIN_ICP_NN_BF16_RERANK) return fail(STEIN_ICP_E_INVALID, "unknown nn mode");
+    if (nq == 0) return STEIN_ICP_OK;
+    if (!q_xyz || !ref_xyz || !idx) return fail(STEIN_ICP_E_INVALID, "a pointer is NULL");
+    const bool bf16 = mode == STEIN_ICP_NN_BF16_RERANK;
+    PairDesc pd{};
+    pd.nq = nq;
+    pd.part_stride = nq;
+    pd.n_ref = n_ref;
+    pd.n_ref_pad = round_up(n_ref, kRefPad);
+    Tiling t;   // the standalone search's shape (stein_icp_nn), fewer chunks if the keys need it
+    t.q = default_queries_per_lane(nq);
+    int64_t chunk = default_chunk(pd.n_ref_pad, nq, t.q, 1);
+    if (bf16 && t.q > 2) t.q = 2;
+    t.w = 4;
+    // scratch layout: flag, descriptor, work table, queries, references,
+    // BF16 fragments, chunk keys (256-byte aligned blocks)
+    const int64_t qblocks = ceil_div(nq, (int64_t)kWave * t.q);
+    const auto a256 = [](int64_t b) { return round_up(b, 256); };
+    const int64_t fixed = 256 + a256(sizeof(PairDesc)) + a256(16 * nq) + a256(16 * pd.n_ref_pad) +
+                          (bf16 ? a256(64 * pd.n_ref_pad) : 0);
+    int64_t chunks = ceil_div(pd.n_ref_pad, chunk);
+    const auto total = [&](int64_t ch) {
+        return fixed + a256((int64_t)sizeof(WorkItem) * qblocks * ch) + a256(8 * ch * nq);
+    };
+    while (chunks > 1 && total(chunks) > (int64_t)kNoAllocScratchBytes) --chunks;
+    if (total(chunks) > (int64_t)kNoAllocScratchBytes)
+        return fail(STEIN_ICP_E_INVALID, "stein_icp_nn_noalloc: the search needs " + std::to_string(total(chunks)) +
+                                             " bytes of scratch, above its 32 MiB");
+    chunk = round_up(ceil_div(pd.n_ref_pad, chunks), 4 * kTile);
+    chunks = ceil_div(pd.n_ref_pad, chunk);
+    pd.chunk = (int32_t)chunk;
+    pd.chunks = (int32_t)chunks;
+    pd.qblocks = (int32_t)qblocks;
+    const int64_t nwork = qblocks * chunks;
+    char* base = nullptr;
+    int rc = scratch_on_device(&base);
+    if (rc) return rc;
+    int64_t off = 0;
+    const auto take = [&](int64_t bytes) {
+        char* p = base + off;
+        off += a256(bytes);
+        return p;
+    };
+    int* fl = (int*)take(256);
+    PairDesc* d_pd = (PairDesc*)take(sizeof(PairDesc));
+    WorkItem* work = (WorkItem*)take((int64_t)sizeof(WorkItem) * nwork);
+    float4* q4 = (float4*)take(16 * nq);
+    float4* r4 = (float4*)take(16 * pd.n_ref_pad);
+    uint4* ap = bf16 ? (uint4*)take(64 * pd.n_ref_pad) : nullptr;
+    uint64_t* keys = (uint64_t*)take(8 * chunks * nq);
+    hipStream_t s = (hipStream_t)hip_stream;
+    int flag = 0;
+    hipLaunchKernelGGL(nn_setup_kernel, grid1d(nwork, 256), dim3(256), 0, s, pd, d_pd, work, nwork, (int32_t)chunks,
+                       fl);
+    hipLaunchKernelGGL(pack_points_kernel, grid1d(nq, 256), dim3(256), 0, s, q_xyz, nq, nq, q4, fl);
+    hipLaunchKernelGGL(pack_points_kernel, grid1d(pd.n_ref_pad, 256), dim3(256), 0, s, ref_xyz, n_ref, pd.n_ref_pad,
+                       r4, fl);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, fl, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(STEIN_ICP_E_DEVICE, std::string("stein_icp_nn_noalloc: ") + hipGetErrorString(e));
+    if (flag) return fail(STEIN_ICP_E_INVALID, "a coordinate is non-finite or above 1e9");
+    if (bf16) {
+        e = launch_bf16_centre(d_pd, r4, n_ref, s);
+        if (e == hipSuccess) e = launch_pack_bf16(d_pd, 1, pd.n_ref_pad / kRefPad, r4, ap, s);
+        NNBf16Args b{};
+        b.work = work;
+        b.pairs = d_pd;
+        b.ref4 = r4;
+        b.apack = ap;
+        b.queries = q4;
+        b.partial = keys;
+        if (e == hipSuccess) e = launch_nn_bf16(t, (unsigned)nwork, b, s);
+    } else {
+        NNArgs a{};
+        a.work = work;
+        a.pairs = d_pd;
+        a.ref4 = r4;
+        a.queries = q4;
+        a.partial = keys;
+        e = launch_nn(t, (unsigned)nwork, a, s);
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(nn_finish_kernel, grid1d(nq, 256), dim3(256), 0, s, keys, q4, r4, pd.n_ref_pad, nq,
+                           (int32_t)chunks, bf16 ? 1 : 0, idx, d2);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(STEIN_ICP_E_DEVICE, std::string("stein_icp_nn_noalloc: ") + hipGetErrorString(e));
+    return STEIN_ICP_OK;
 }
 
 namespace {

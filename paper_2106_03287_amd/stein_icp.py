@@ -63,7 +63,8 @@ EXPORTS = [
     "stein_icp_get_diagnostics", "stein_icp_shape", "stein_icp_nn_tiling", "stein_icp_set_nn_tiling",
     "stein_icp_stage_times", "stein_icp_time_nn", "stein_icp_nn_rescans",
     "stein_icp_destroy",
-    "stein_icp_last_error", "stein_icp_nn", "stein_icp_make_schedule", "stein_icp_make_init",
+    "stein_icp_last_error", "stein_icp_nn", "stein_icp_nn_noalloc", "stein_icp_make_schedule",
+    "stein_icp_make_init",
     "stein_icp_knn", "stein_icp_normals", "stein_icp_get_normals", "stein_icp_posterior_scores",
 ]
 
@@ -103,6 +104,7 @@ def lib():
     L.stein_icp_last_error.argtypes = []
     L.stein_icp_last_error.restype = C.c_char_p
     L.stein_icp_nn.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
+    L.stein_icp_nn_noalloc.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
     L.stein_icp_knn.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
     L.stein_icp_normals.argtypes = [vp, i64, i32, vp, vp, vp]
     L.stein_icp_get_normals.argtypes = [vp, vp, vp]
@@ -322,6 +324,23 @@ def stein_icp_nn(q, ref, mode=NN_FP32, stream=None):
     d2 = torch.empty(q.shape[0], dtype=torch.float32, device=q.device)
     _check("stein_icp_nn", lib().stein_icp_nn(_ptr(q), q.shape[0], _ptr(ref), ref.shape[0],
                                               int(mode), _ptr(idx), _ptr(d2), _stream(stream)))
+    return idx, d2
+
+
+def stein_icp_nn_noalloc(q, ref, mode=NN_FP32, idx=None, d2=None, stream=None):
+    """stein_icp_nn on the library's own scratch (no device allocation in the
+    library); idx / d2 may be given (int32 / float32, nq each) to write into."""
+    import torch
+    _need(q, torch.float32, (q.shape[0], 3), "q")
+    _need(ref, torch.float32, (ref.shape[0], 3), "ref")
+    if idx is None:
+        idx = torch.empty(q.shape[0], dtype=torch.int32, device=q.device)
+    if d2 is None:
+        d2 = torch.empty(q.shape[0], dtype=torch.float32, device=q.device)
+    _need(idx, torch.int32, (q.shape[0],), "idx")
+    _need(d2, torch.float32, (q.shape[0],), "d2")
+    _check("stein_icp_nn_noalloc", lib().stein_icp_nn_noalloc(_ptr(q), q.shape[0], _ptr(ref), ref.shape[0],
+                                                              int(mode), _ptr(idx), _ptr(d2), _stream(stream)))
     return idx, d2
 
 
