@@ -154,6 +154,16 @@ int stein_icp_step(stein_icp_ctx *ctx, int32_t n_iters, void *hip_stream);
 /* Copy the particles to device FP64 out (n_pairs x K x 6). Asynchronous. */
 int stein_icp_particles(const stein_icp_ctx *ctx, double *out, void *hip_stream);
 
+/* FP32 particle I/O (the problem statement's K x 6 FP32 particles, beside
+ * the FP64 state the library keeps):
+ * stein_icp_particles_f32: the particles rounded to FP32 (nearest), device
+ *   FP32 n_pairs x K x 6 out. Asynchronous.
+ * stein_icp_set_particles_f32: start again from device FP32 n_pairs x K x 6
+ *   particles (widened exactly to FP64), Adam moments zero, step count 0.
+ *   Blocking: a non-finite value gives E_INVALID with the context unchanged. */
+int stein_icp_particles_f32(const stein_icp_ctx *ctx, float *out, void *hip_stream);
+int stein_icp_set_particles_f32(stein_icp_ctx *ctx, const float *theta, void *hip_stream);
+
 /* Read the optimiser state: device FP64 theta, Adam first and second moments
  * (each n_pairs x K x 6; any may be NULL) and the host step count t (may be
  * NULL). Blocking (synchronises `hip_stream`). */

@@ -128,6 +128,26 @@ __global__ void check_finite_kernel(const double* __restrict__ in, int64_t n, in
     if (i < n && !isfinite(in[i])) atomicOr(bad, 4);
 }
 
+// FP32 particles in (widened exactly to FP64) and out (rounded to nearest),
+// n values; the input side flags (bit 4) a non-finite value.
+__global__ void check_finite_f32_kernel(const float* __restrict__ in, int64_t n, int* __restrict__ bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(in[i])) atomicOr(bad, 4);
+}
+
+__global__ void widen_f32_kernel(const float* __restrict__ in, int64_t n, double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (double)in[i];
+}
+
+__global__ void narrow_f64_kernel(const double* __restrict__ in, int64_t n, float* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
 __global__ void fill_i32_kernel(int* __restrict__ out, int64_t n, int v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

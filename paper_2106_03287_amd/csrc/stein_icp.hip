@@ -1123,6 +1123,38 @@ int stein_icp_set_state(stein_icp_ctx* ctx, const double* theta, const double* m
     return STEIN_ICP_OK;
 }
 
+int stein_icp_particles_f32(const stein_icp_ctx* ctx, float* out, void* hip_stream)
+{
+    if (!ctx || !out) return fail(STEIN_ICP_E_INVALID, "ctx or out is NULL");
+    const int64_t n = (int64_t)ctx->P * ctx->K * 6;
+    hipLaunchKernelGGL(narrow_f64_kernel, grid1d(n, 256), dim3(256), 0, (hipStream_t)hip_stream, ctx->theta, n, out);
+    HIP_TRY(hipGetLastError());
+    return STEIN_ICP_OK;
+}
+
+int stein_icp_set_particles_f32(stein_icp_ctx* ctx, const float* theta, void* hip_stream)
+{
+    if (!ctx || !theta) return fail(STEIN_ICP_E_INVALID, "ctx or theta is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t n = (int64_t)ctx->P * ctx->K * 6;
+    int bad = 0;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, ctx->flag, (int64_t)1, 0);
+    hipLaunchKernelGGL(check_finite_f32_kernel, grid1d(n, 256), dim3(256), 0, s, theta, n, ctx->flag);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&bad, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bad) return fail(STEIN_ICP_E_INVALID, "a particle is non-finite");
+    hipLaunchKernelGGL(widen_f32_kernel, grid1d(n, 256), dim3(256), 0, s, theta, n, ctx->theta);
+    hipLaunchKernelGGL(fill_f64_kernel, grid1d(n, 256), dim3(256), 0, s, ctx->mom, n, 0.0);
+    hipLaunchKernelGGL(fill_f64_kernel, grid1d(n, 256), dim3(256), 0, s, ctx->vel, n, 0.0);
+    hipLaunchKernelGGL(fill_i64_kernel, grid1d(ctx->P, 256), dim3(256), 0, s, ctx->step, (int64_t)ctx->P, (int64_t)0);
+    hipLaunchKernelGGL(pose_kernel, grid1d((int64_t)ctx->P * ctx->K, 256), dim3(256), 0, s, ctx->theta, ctx->pose,
+                       (int64_t)ctx->P * ctx->K);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(enqueue_queries(ctx, s));
+    return STEIN_ICP_OK;
+}
+
 int stein_icp_get_diagnostics(const stein_icp_ctx* ctx, double* gbar, double* phi, double* h, int32_t* match,
                               void* hip_stream)
 {

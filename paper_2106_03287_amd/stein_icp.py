@@ -60,6 +60,7 @@ class stein_icp_config(C.Structure):
 EXPORTS = [
     "stein_icp_default_config", "stein_icp_init", "stein_icp_batch_init", "stein_icp_step",
     "stein_icp_particles", "stein_icp_get_state", "stein_icp_set_state",
+    "stein_icp_particles_f32", "stein_icp_set_particles_f32",
     "stein_icp_get_diagnostics", "stein_icp_shape", "stein_icp_nn_tiling", "stein_icp_set_nn_tiling",
     "stein_icp_stage_times", "stein_icp_time_nn", "stein_icp_nn_rescans",
     "stein_icp_destroy",
@@ -90,6 +91,8 @@ def lib():
     L.stein_icp_step.argtypes = [vp, i32, vp]
     L.stein_icp_particles.argtypes = [vp, vp, vp]
     L.stein_icp_get_state.argtypes = [vp, vp, vp, vp, C.POINTER(i64), vp]
+    L.stein_icp_particles_f32.argtypes = [vp, vp, vp]
+    L.stein_icp_set_particles_f32.argtypes = [vp, vp, vp]
     L.stein_icp_set_state.argtypes = [vp, vp, vp, vp, i64, vp]
     L.stein_icp_get_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp]
     L.stein_icp_shape.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
@@ -257,6 +260,25 @@ def stein_icp_set_state(ctx, theta, mom=None, vel=None, t=0, stream=None):
                                                             int(t), _stream(stream)))
 
 
+def stein_icp_particles_f32(ctx, stream=None):
+    """Particles rounded to FP32, (P, K, 6) float32 on the device."""
+    import torch
+    P, K, _ = stein_icp_shape(ctx)
+    out = torch.empty((P, K, 6), dtype=torch.float32, device="cuda")
+    _check("stein_icp_particles_f32", lib().stein_icp_particles_f32(ctx, _ptr(out), _stream(stream)))
+    return out
+
+
+def stein_icp_set_particles_f32(ctx, theta, stream=None):
+    """Start again from FP32 particles (P * K * 6 float32 on the device)."""
+    import torch
+    P, K, _ = stein_icp_shape(ctx)
+    _need(theta, torch.float32, None, "theta")
+    if theta.numel() != P * K * 6:
+        raise ValueError("theta must hold n_pairs * K * 6 values")
+    _check("stein_icp_set_particles_f32", lib().stein_icp_set_particles_f32(ctx, _ptr(theta), _stream(stream)))
+
+
 def stein_icp_get_diagnostics(ctx, stream=None):
     import torch
     P, K, m = stein_icp_shape(ctx)
@@ -420,6 +442,12 @@ class SteinICP:
 
     def particles(self, out=None, stream=None):
         return stein_icp_particles(self.ctx, out, stream)
+
+    def particles_f32(self):
+        return stein_icp_particles_f32(self.ctx)
+
+    def set_particles_f32(self, theta):
+        stein_icp_set_particles_f32(self.ctx, theta)
 
     def get_state(self):
         return stein_icp_get_state(self.ctx)

@@ -258,6 +258,35 @@ def test_batched_context_matches_single_contexts_and_oracle():
         assert_poses_close(got[i], oracle_run(p, 6))
 
 
+def test_fp32_particle_input_and_output():
+    """FP32 K x 6 particles in (widened exactly, a fresh start) and out
+    (rounded to nearest): a solve started from FP32 particles equals one
+    started from the same values in FP64, and the FP32 output is the FP64
+    state rounded once; non-finite input is refused with the state kept."""
+    prob = synth.make_problem("cuboid", 15, K=24, T=6)
+    th32 = prob.theta0.astype(np.float32)
+    a = gpu_solver(prob)
+    a.step(3)
+    a.set_particles_f32(dev(th32))
+    a.step(prob.T)
+    b = gpu_solver(prob)
+    b.set_state(dev(th32.astype(np.float64)))
+    b.step(prob.T)
+    np.testing.assert_array_equal(a.particles().cpu().numpy(), b.particles().cpu().numpy())
+    assert a.get_state()[3] == prob.T
+    f = a.particles_f32().cpu().numpy()
+    np.testing.assert_array_equal(f, a.particles().cpu().numpy().astype(np.float32))
+    bad = th32.copy()
+    bad[2, 4] = np.inf
+    before = a.particles().clone()
+    with pytest.raises(S.SteinICPError) as e:
+        a.set_particles_f32(dev(bad))
+    assert e.value.code == S.E_INVALID
+    assert torch.equal(a.particles(), before)
+    a.close()
+    b.close()
+
+
 def test_library_drawn_particles_and_schedule():
     prob = synth.make_problem("cuboid", 11, T=5)
     cfg = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m, schedule_rows=5,
