@@ -29,10 +29,14 @@ NORMAL_K = 10               # neighbours per normal of the point-to-plane metric
 # Algorithmic work of one pair evaluation of Eq. 1: the FP32 squared distance,
 # 3 subtractions, 1 multiply and 2 fused multiply-adds (2 flops each) = 8 flops.
 FLOPS_PER_PAIR = 8
-# Issued matrix-core work of the BF16 screen: two 32x32x16 BF16 products
-# (2 * 32 * 32 * 16 flops each) per 32 references x 32 queries = 64 flops per
-# pair (24 of the 32 K slots carry the three-part split, 8 are zero).
-MFMA_FLOPS_PER_PAIR_ISSUED = 64
+# Issued matrix-core work of the screens per pair: BF16 x 3 takes two
+# 32x32x16 BF16 products (2 * 32 * 32 * 16 flops each) per 32 references x
+# 32 queries = 64 flops (24 of its 32 K slots carry the three-part split);
+# FP16 x 2 takes one 32x32x16 FP16 product = 32 flops (15 of 16 K slots).
+MFMA_FLOPS_PER_PAIR_ISSUED = {"bf16": 64, "f16": 32}
+SCREENS = ("bf16", "f16")
+NN_MODE = {"fp32": 0, "bf16": 1, "f16": 2}     # STEIN_ICP_NN_*
+DTYPE = {"fp32": "f32", "bf16": "bf16+f32", "f16": "f16+f32"}
 NN_SOURCES = ["paper_2106_03287_amd/csrc/nn.hpp", "paper_2106_03287_amd/csrc/common.hpp"]
 NN_BF16_SOURCES = NN_SOURCES + ["paper_2106_03287_amd/csrc/nn_bf16.hpp"]
 
@@ -80,7 +84,7 @@ def gpu_info(host):
 def nn_source_sha(nn="fp32"):
     import hashlib
     h = hashlib.sha256()
-    for f in (NN_BF16_SOURCES if nn == "bf16" else NN_SOURCES):
+    for f in (NN_BF16_SOURCES if nn in SCREENS else NN_SOURCES):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -114,11 +118,12 @@ def nn_roofline(nn, pairs_per_launch, nn_ms, counters):
            "pair_evals_per_launch": pairs_per_launch,
            "hbm_gbps": None if traffic is None else round(traffic / t / 1e9, 1),
            "hbm_frac": None if traffic is None else round(traffic / t / 1e9 / HBM_PEAK_GBPS, 4)}
-    if nn == "bf16":
-        issued = pairs_per_launch * MFMA_FLOPS_PER_PAIR_ISSUED / t / 1e12
+    if nn in SCREENS:
+        per = MFMA_FLOPS_PER_PAIR_ISSUED[nn]
+        issued = pairs_per_launch * per / t / 1e12
         out.update(bound="mfma", peak=MFMA_BF16_PEAK_TFLOPS, frac=round(useful / MFMA_BF16_PEAK_TFLOPS, 4),
-                   kernel="nn_bf16_kernel",
-                   issued_mfma={"flops_per_pair": MFMA_FLOPS_PER_PAIR_ISSUED, "achieved": round(issued, 3),
+                   kernel="nn_bf16_kernel (%s)" % ("BF16 x 3" if nn == "bf16" else "FP16 x 2"),
+                   issued_mfma={"flops_per_pair": per, "achieved": round(issued, 3),
                                 "frac": round(issued / MFMA_BF16_PEAK_TFLOPS, 4)},
                    mfma_busy=counters.get("mfma_busy"))
     else:
@@ -153,21 +158,25 @@ def cpu_baseline(prob, budget_s=15.0, plane=False):
                       f"the T={prob.T} solve"}
 
 
-# NN shapes (queries per lane, wavefronts per workgroup, chunk, persistent
-# workgroups per CU) pinned from a sweep of the tuner's space on one MI355X
-# (full solves, median of 3); the runner-up shapes are within 2 %
-# search mode of --nn auto: the certified BF16 screen returns the FP32 search's
-# answers bit for bit; measured faster than the FP32 search on the Kinect
-# (1.56x on the NN launch), LiDAR (1.38x), batched (1.5x) and Monte-Carlo
-# workloads, and not on the small cuboid clouds, where the search is
-# latency-bound
-AUTO_NN = {"cuboid": "fp32", "kinect": "bf16", "lidar": "bf16", "mc": "bf16", "batched": "bf16"}
+# Search mode of --nn auto. The certified screens return the FP32 search's
+# answers bit for bit. The FP16 x 2 screen (one matrix product per block)
+# measured faster than the BF16 x 3 screen (two) on the NN launch: LiDAR
+# 1.22 against 1.64 ms, Kinect 36.9 against 44.3 us; both beat the FP32
+# search there, and neither does on the small cuboid clouds, where the search
+# is latency-bound.
+AUTO_NN = {"cuboid": "fp32", "kinect": "f16", "lidar": "f16", "mc": "f16", "batched": "f16"}
 
+# NN shapes (queries per lane, wavefronts per workgroup, chunk, persistent
+# workgroups per CU) pinned from sweeps of the NN launch on one MI355X: LiDAR
+# FP16 x 2 1.22 ms with one chunk (1.24 with two, 1.44 with four), BF16 x 3
+# 1.64 ms with two (1.77 with four); Kinect one chunk of the whole reference.
 PINNED_TILING = {
     ("kinect", "fp32"): "4,16,2048,2",
     ("kinect", "bf16"): "2,8,20096,0",
+    ("kinect", "f16"): "2,8,20096,0",
     ("lidar", "fp32"): "4,8,4096,0",
-    ("lidar", "bf16"): "2,8,25088,0",
+    ("lidar", "bf16"): "2,8,50176,0",
+    ("lidar", "f16"): "2,8,100000,0",
 }
 
 
@@ -181,7 +190,7 @@ def main():
     ap.add_argument("--pairs", type=int, default=64, help="pairs of the batched and proposal workloads")
     ap.add_argument("--workers", type=int, default=16,
                     help="host processes generating the proposal workload's pairs (1: in process)")
-    ap.add_argument("--nn", default="auto", choices=["auto", "fp32", "bf16"],
+    ap.add_argument("--nn", default="auto", choices=["auto", "fp32", "bf16", "f16"],
                     help="nearest-neighbour search: FP32, or the certified BF16 matrix-core screen (the same "
                          "answers); auto takes the faster for the workload")
     ap.add_argument("--metric", default="point", choices=["point", "plane"],
@@ -237,7 +246,7 @@ def main():
     cfg = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m,
                                      schedule_rows=prob.schedule.shape[0], lr=prob.lr,
                                      autotune=0 if args.tiling else args.autotune,
-                                     nn_mode=S.NN_BF16_RERANK if args.nn == "bf16" else S.NN_FP32,
+                                     nn_mode=NN_MODE[args.nn],
                                      metric=S.METRIC_PLANE if args.metric == "plane" else S.METRIC_POINT,
                                      normal_k=NORMAL_K)
     t_init = time.perf_counter()
@@ -286,7 +295,7 @@ def main():
     pairs_per_launch = prob.K * prob.m * M
     roofline = nn_roofline(args.nn, pairs_per_launch, nn_ms, measured_counters(prob.name, tiling, args.nn))
     mismatch, identical = None, None
-    if args.nn == "bf16":
+    if args.nn in SCREENS:
         # against the FP32 search from the same state: the first iteration's
         # matches, and the particles after the whole solve (bit for bit)
         S.stein_icp_set_state(sol.ctx, theta0, zeros, zeros, 0)
@@ -316,7 +325,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16+f32" if args.nn == "bf16" else "f32",
+        "dtype": DTYPE[args.nn],
         "data": "synthetic",
         "config": {"workload": prob.name, "K": prob.K, "m": prob.m, "T": prob.T,
                    "N": len(prob.pair.src), "M": M, "nn": args.nn, "metric": args.metric,
@@ -357,7 +366,7 @@ def run_batched(args):
     th0 = dev(np.stack([p.theta0 for p in probs]))
     cfg = S.stein_icp_default_config(num_particles=K, batch_size=m, schedule_rows=probs[0].schedule.shape[0],
                                      lr=probs[0].lr, autotune=0 if args.tiling else args.autotune,
-                                     nn_mode=S.NN_BF16_RERANK if args.nn == "bf16" else S.NN_FP32)
+                                     nn_mode=NN_MODE[args.nn])
     t_init = time.perf_counter()
     batch = S.SteinICP.batch(cfg, srcs, refs, th0, scheds)
     init_ms = (time.perf_counter() - t_init) * 1e3
@@ -407,7 +416,7 @@ def run_batched(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16+f32" if args.nn == "bf16" else "f32",
+        "dtype": DTYPE[args.nn],
         "data": "synthetic",
         "config": {"workload": "batched", "pairs": P, "K": K, "m": m, "T": T,
                    "M_range": [min(len(p.pair.ref) for p in probs), max(len(p.pair.ref) for p in probs)],
@@ -448,7 +457,7 @@ def run_mc(args):
     T = args.iters or prob.T
     R = args.runs
     nn = "bf16" if args.nn == "auto" else args.nn
-    nn_mode = S.NN_BF16_RERANK if nn == "bf16" else S.NN_FP32
+    nn_mode = NN_MODE[nn]
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     src, ref = dev(prob.pair.src), dev(prob.pair.ref)
     cfg = S.stein_icp_default_config(num_particles=1, batch_size=prob.m, schedule_rows=T, lr=prob.lr,
@@ -465,8 +474,8 @@ def run_mc(args):
     scfg = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m, schedule_rows=prob.schedule.shape[0],
                                       lr=prob.lr, nn_mode=nn_mode)
     stein = S.SteinICP(scfg, src, ref, dev(prob.theta0), dev(prob.schedule))
-    if nn == "bf16":
-        stein.set_tiling(*[int(x) for x in PINNED_TILING[("kinect", "bf16")].split(",")])
+    if nn in SCREENS:
+        stein.set_tiling(*[int(x) for x in PINNED_TILING[("kinect", nn)].split(",")])
     sz = torch.zeros_like(dev(prob.theta0))
 
     def solve_mc():
@@ -518,7 +527,7 @@ def run_mc(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16+f32" if nn == "bf16" else "f32",
+        "dtype": DTYPE[nn],
         "data": "synthetic",
         "config": {"workload": "mc", "pair": "kinect", "runs": R, "K": 1, "m": prob.m, "T": T, "M": M,
                    "start_box": [synth.MC_HALF_TRANS, synth.MC_HALF_ROT], "nn": nn,

@@ -53,8 +53,13 @@ extern "C" {
  * coordinates split into three BF16 parts), the best re-ranked with the FP32
  * distance above, and every answer certified against a bound on the screen's
  * error; a query whose certificate fails is searched again in FP32. Far from
- * the centroid the bound widens and more queries take the FP32 path. */
-enum { STEIN_ICP_NN_FP32 = 0, STEIN_ICP_NN_BF16_RERANK = 1 };
+ * the centroid the bound widens and more queries take the FP32 path.
+ * F16_RERANK: the same certified screen with the centred coordinates scaled
+ * by a power of two and split into two FP16 parts (FP16's 11-bit significand
+ * carries in two parts what BF16 needs three for): one matrix product per
+ * block of references instead of two, with an error bound of the same size.
+ * All three modes return the same answers. */
+enum { STEIN_ICP_NN_FP32 = 0, STEIN_ICP_NN_BF16_RERANK = 1, STEIN_ICP_NN_F16_RERANK = 2 };
 /* Update rule: Adam on -phi (Sec. V), or theta += lr * phi (Eq. 12). */
 enum { STEIN_ICP_OPT_ADAM = 0, STEIN_ICP_OPT_SGD = 1 };
 /* Kernel bandwidth: median heuristic h = med^2 / ln K over the K(K-1)/2

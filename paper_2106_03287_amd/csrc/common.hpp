@@ -33,7 +33,7 @@ struct PairDesc {
     int32_t chunks;     // reference chunks, one partial argmin each
     int32_t chunk;      // references per chunk (multiple of kRefPad)
     int32_t qblocks;    // query blocks of kWave * Q queries
-    int32_t pad_;
+    int32_t sexp;       // FP16 screen: centred coordinates are scaled by 2^sexp
 };
 
 // Work item of the NN kernel: NN group, query block, reference chunk. An NN

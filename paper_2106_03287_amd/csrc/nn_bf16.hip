@@ -11,21 +11,31 @@ bool nn_bf16_shape_ok(int q, int w)
     return (q == 1 && (w == 4 || w == 8 || w == 16)) || (q == 2 && (w == 4 || w == 8));
 }
 
-hipError_t launch_nn_bf16_kernel(int q, int w, unsigned grid, const NNBf16Args& a, hipStream_t s)
+template <int FMT>
+static void launch_fmt(int q, int w, unsigned grid, const NNBf16Args& a, hipStream_t s)
 {
-    if (!nn_bf16_shape_ok(q, w)) return hipErrorInvalidValue;
     if (q == 1) {
         switch (w) {
-        case 4: hipLaunchKernelGGL((nn_bf16_kernel<1, 4>), dim3(grid), dim3(kWave * 4), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((nn_bf16_kernel<1, 8>), dim3(grid), dim3(kWave * 8), 0, s, a); break;
-        default: hipLaunchKernelGGL((nn_bf16_kernel<1, 16>), dim3(grid), dim3(kWave * 16), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((nn_bf16_kernel<1, 4, FMT>), dim3(grid), dim3(kWave * 4), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((nn_bf16_kernel<1, 8, FMT>), dim3(grid), dim3(kWave * 8), 0, s, a); break;
+        default: hipLaunchKernelGGL((nn_bf16_kernel<1, 16, FMT>), dim3(grid), dim3(kWave * 16), 0, s, a); break;
         }
     } else {
-        if (w == 4) hipLaunchKernelGGL((nn_bf16_kernel<2, 4>), dim3(grid), dim3(kWave * 4), 0, s, a);
-        else hipLaunchKernelGGL((nn_bf16_kernel<2, 8>), dim3(grid), dim3(kWave * 8), 0, s, a);
+        if (w == 4) hipLaunchKernelGGL((nn_bf16_kernel<2, 4, FMT>), dim3(grid), dim3(kWave * 4), 0, s, a);
+        else hipLaunchKernelGGL((nn_bf16_kernel<2, 8, FMT>), dim3(grid), dim3(kWave * 8), 0, s, a);
     }
+}
+
+hipError_t launch_nn_bf16_kernel(int q, int w, int fmt, unsigned grid, const NNBf16Args& a, hipStream_t s)
+{
+    if (!nn_bf16_shape_ok(q, w)) return hipErrorInvalidValue;
+    if (fmt == kFmtF16x2) launch_fmt<kFmtF16x2>(q, w, grid, a, s);
+    else if (fmt == kFmtBf16x3) launch_fmt<kFmtBf16x3>(q, w, grid, a, s);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
+
+int f16_screen_exponent_host(float R) { return f16_screen_exponent(R); }
 
 hipError_t launch_bf16_centre(PairDesc* pair, const float4* ref4, int64_t n_ref, hipStream_t s)
 {
@@ -34,11 +44,12 @@ hipError_t launch_bf16_centre(PairDesc* pair, const float4* ref4, int64_t n_ref,
 }
 
 hipError_t launch_pack_bf16(const PairDesc* pairs, int32_t n_pairs, int64_t max_blocks, const float4* ref4,
-                            uint4* apack, hipStream_t s)
+                            uint4* apack, int fmt, hipStream_t s)
 {
     if (n_pairs < 1 || max_blocks < 1) return hipSuccess;
-    hipLaunchKernelGGL(pack_bf16_refs_kernel, dim3((unsigned)((max_blocks + 3) / 4), (unsigned)n_pairs), dim3(256), 0,
-                       s, pairs, ref4, apack);
+    const dim3 grid((unsigned)((max_blocks + 3) / 4), (unsigned)n_pairs);
+    if (fmt == kFmtF16x2) hipLaunchKernelGGL(pack_f16_refs_kernel, grid, dim3(256), 0, s, pairs, ref4, apack);
+    else hipLaunchKernelGGL(pack_bf16_refs_kernel, grid, dim3(256), 0, s, pairs, ref4, apack);
     return hipGetLastError();
 }
 

@@ -113,6 +113,101 @@ __device__ __forceinline__ void slot_fragments(const float c[3], bool ref, int h
     }
 }
 
+// ---------------------------------------------------------------- FP16 x 2
+// The second screen format. Centred coordinates are scaled by 2^sexp (exact:
+// a power of two, chosen per pair so the largest centred reference norm R
+// becomes at most 32) and split into two FP16 parts, x = h + m + rest with
+// |m| <= 2^-11 |x| and |rest| <= 2^-22 |x| + 2^-25 (FP16 has an 11-bit
+// significand, so two parts carry what BF16 needs three for). The norms take
+// three FP16 parts. 15 of the 16 K slots of one 32 x 32 x 16 FP16 product:
+//    k 0- 2: r_h * -2 q_h      k  9-11: |r|^2 (h, m, l) * 1
+//    k 3- 5: r_h * -2 q_m      k 12-14: 1 * |q|^2 (h, m, l)
+//    k 6- 8: r_m * -2 q_h      k 15: 0
+// Error (scaled units, q' and r' the scaled centred points, u = 2^-24): the
+// dropped cross parts m_q m_r, h_q rest_r, rest_q h_r, ... with the factor 2
+// give at most 24.1 u |q'||r'| + 3.5 2^-25 (|q'| + |r'|); the norms' FP32
+// rounding and split 3.1 u (|q'|^2 + |r'|^2) + 2^-24; the FP32 sum of the
+// exact products 16.1 u (|q'| + |r'|)^2; the centring 2.1 u (|q'| + |r'|)^2;
+// the FP32 direct difference of the rerank 6.2 u (|q'| + |r'|)^2. All told
+// |S - s^2 F| <= 34 u (|q'| + |r'|)^2 + 2^-22 (|q'| + |r'| + 1); the
+// certificate uses 40 u in place of 34 u. A query whose scaled centred norm
+// exceeds kF16QueryMax (its norm would leave FP16's comfortable range) is
+// not screened: its lanes fail the certificate and search in FP32.
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+
+constexpr float kF16QueryMax = 200.0f;
+
+__device__ __forceinline__ uint16_t f16_bits(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+__device__ __forceinline__ float f16_float(uint16_t v) { return (float)__builtin_bit_cast(_Float16, v); }
+
+// x = h + m (+ rest) with h, m FP16 (the subtraction is exact in FP32).
+__device__ __forceinline__ void split2_f16(float x, uint16_t& h, uint16_t& m)
+{
+#pragma clang fp contract(off)
+    h = f16_bits(x);
+    m = f16_bits(x - f16_float(h));
+}
+
+__device__ __forceinline__ void split3_f16(float x, uint16_t& h, uint16_t& m, uint16_t& l)
+{
+#pragma clang fp contract(off)
+    h = f16_bits(x);
+    const float r1 = x - f16_float(h);
+    m = f16_bits(r1);
+    l = f16_bits(r1 - f16_float(m));
+}
+
+// Scaled centred coordinates: c * 2^e (exact for |e| <= 60 on the FP32
+// values the screen sees).
+__device__ __forceinline__ void scale_coords(float c[3], int e)
+{
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = ldexpf(c[d], e);
+}
+
+// The FP16 fragment of one side for lane half hh: K slots 8 hh .. 8 hh + 7
+// of the table above. c: scaled centred coordinates.
+__device__ __forceinline__ void slot_fragment_f16(const float c[3], bool ref, int hh, u16x8_t& v)
+{
+#pragma clang fp contract(off)
+    constexpr uint16_t kOne = 0x3C00, kZero = 0;
+    uint16_t h[3], m[3], nh, nm, nl;
+    for (int d = 0; d < 3; ++d) split2_f16(c[d], h[d], m[d]);
+    const float n = (c[0] * c[0] + c[1] * c[1]) + c[2] * c[2];
+    split3_f16(n, nh, nm, nl);
+    uint16_t t[16];
+    if (ref) {
+        for (int d = 0; d < 3; ++d) {
+            t[d] = h[d]; t[3 + d] = h[d]; t[6 + d] = m[d];
+            t[12 + d] = kOne;
+        }
+        t[9] = nh; t[10] = nm; t[11] = nl;
+    } else {
+        // -2 x of an FP16 value is exact in FP32 and again an FP16 value
+        auto m2 = [](uint16_t x) -> uint16_t { return f16_bits(-2.0f * f16_float(x)); };
+        for (int d = 0; d < 3; ++d) {
+            t[d] = m2(h[d]); t[3 + d] = m2(m[d]); t[6 + d] = m2(h[d]);
+            t[9 + d] = kOne;
+        }
+        t[12] = nh; t[13] = nm; t[14] = nl;
+    }
+    t[15] = kZero;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = hh ? t[8 + k] : t[k];
+}
+
+// Scale exponent of the FP16 screen for a largest centred norm R: the
+// largest e with R 2^e <= 32 (R = f 2^x, f in [0.5, 1): e = 5 - x), within
+// [-60, 60]; 0 for R = 0.
+__host__ __device__ inline int f16_screen_exponent(float R)
+{
+    if (!(R > 0.0f) || !(R < 3.0e38f)) return 0;
+    int x = 0;
+    (void)frexpf(R, &x);
+    const int e = 5 - x;
+    return e < -60 ? -60 : (e > 60 ? 60 : e);
+}
+
 constexpr int kBlk = kRefPad;   // references per block of the screen (the A operand's 32 rows)
 
 // Row of the 32-reference block held by output t (0..15) of a lane in half h
@@ -145,6 +240,41 @@ __global__ void pack_bf16_refs_kernel(const PairDesc* __restrict__ pairs, const 
     uint4* out = apack + pd.apack_off + blk * 2 * kWave + lane;
     out[0] = __builtin_bit_cast(uint4, v0);
     out[kWave] = __builtin_bit_cast(uint4, v1);
+}
+
+// The FP16 screen's A fragments: one uint4 per lane, a block is the 64
+// lanes' fragments in order (1 KB per 32 references).
+__global__ void pack_f16_refs_kernel(const PairDesc* __restrict__ pairs, const float4* __restrict__ ref4,
+                                     uint4* __restrict__ apack)
+{
+    const PairDesc pd = pairs[blockIdx.y];
+    const int64_t blk = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    if (blk >= pd.n_ref_pad / kBlk) return;
+    const float4 r = ref4[pd.ref_off + blk * kBlk + (lane & 31)];
+    float c[3];
+    {
+#pragma clang fp contract(off)
+        c[0] = r.x - pd.c0[0];
+        c[1] = r.y - pd.c0[1];
+        c[2] = r.z - pd.c0[2];
+    }
+    scale_coords(c, pd.sexp);
+    u16x8_t v;
+    slot_fragment_f16(c, true, lane >> 5, v);
+    if (blk * kBlk + (lane & 31) >= pd.n_ref) {
+        // padding: no cross parts and the largest finite FP16 value in the
+        // three norm slots, so S exceeds every real distance (scaled real
+        // distances are below (kF16QueryMax + 32)^2 < 3 x 65504)
+        constexpr uint16_t kMaxF16 = 0x7BFF;
+        const int hh = lane >> 5;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int slot = 8 * hh + k;
+            v[k] = (slot >= 9 && slot <= 11) ? kMaxF16 : (slot >= 12 && slot <= 14 ? (uint16_t)0x3C00 : (uint16_t)0);
+        }
+    }
+    apack[pd.apack_off + blk * kWave + lane] = __builtin_bit_cast(uint4, v);
 }
 
 // Centre of the screen found on the device, for callers that hand the
@@ -207,14 +337,16 @@ __global__ __launch_bounds__(kCentreThreads) void bf16_centre_kernel(PairDesc* _
         pd->c0[1] = cy;
         pd->c0[2] = cz;
         pd->c0[3] = nextafterf((float)(sqrt(m) * (1.0 + 0x1.0p-20)), __builtin_inff());
+        pd->sexp = f16_screen_exponent(pd->c0[3]);
     }
 }
 
 // A work item holds 64 Q queries (as in the FP32 search), taken as 2 Q groups
 // of 32 by every wavefront of the workgroup.
-template <int Q, int W>
+template <int Q, int W, int FMT>
 __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem w, uint64_t (*sk)[kWave * Q])
 {
+    constexpr bool F16 = FMT == kFmtF16x2;
     constexpr int G = 2 * Q;   // query groups of 32
     const PairDesc pd = a.pairs[w.pair];
     const int lane = threadIdx.x & (kWave - 1);
@@ -223,7 +355,9 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     const int64_t qbase = (int64_t)w.qblock * kWave * Q;
     const int j = lane & 31, h = lane >> 5;
 
-    bf16x8_t b0[G], b1[G];
+    bf16x8_t b0[G], b1[G];   // BF16 x 3
+    f16x8_t e0[G];           // FP16 x 2
+    uint32_t far_q = 0u;     // FP16 x 2: groups whose query lies beyond kF16QueryMax (not screened)
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const int64_t qi = qbase + 32 * g + j;
@@ -235,10 +369,24 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
             c[1] = qf.y - pd.c0[1];
             c[2] = qf.z - pd.c0[2];
         }
-        u16x8_t v0, v1;
-        slot_fragments(c, false, h, v0, v1);
-        b0[g] = __builtin_bit_cast(bf16x8_t, v0);
-        b1[g] = __builtin_bit_cast(bf16x8_t, v1);
+        if constexpr (F16) {
+            scale_coords(c, pd.sexp);
+            const bool far = !(fabsf(c[0]) <= kF16QueryMax && fabsf(c[1]) <= kF16QueryMax &&
+                               fabsf(c[2]) <= kF16QueryMax &&
+                               (c[0] * c[0] + c[1] * c[1]) + c[2] * c[2] <= kF16QueryMax * kF16QueryMax);
+            if (far) {
+                c[0] = c[1] = c[2] = 0.0f;   // finite fragments; the lane searches in FP32 instead
+                far_q |= 1u << g;
+            }
+            u16x8_t v;
+            slot_fragment_f16(c, false, h, v);
+            e0[g] = __builtin_bit_cast(f16x8_t, v);
+        } else {
+            u16x8_t v0, v1;
+            slot_fragments(c, false, h, v0, v1);
+            b0[g] = __builtin_bit_cast(bf16x8_t, v0);
+            b1[g] = __builtin_bit_cast(bf16x8_t, v1);
+        }
     }
 
     const int64_t c0 = (int64_t)w.chunk * pd.chunk;
@@ -247,8 +395,11 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     const int32_t nblk = (int32_t)((cend - c0) / kBlk);
     const int32_t t0 = uniform((int32_t)(((int64_t)nblk * wave) / W));
     const int32_t t1 = uniform((int32_t)(((int64_t)nblk * (wave + 1)) / W));
-    const uint4* __restrict__ ap0 = a.apack + pd.apack_off + (c0 / kBlk) * 2 * kWave + lane;
-    const uint4* __restrict__ ap1 = a.apack + pd.apack_off + (c0 / kBlk) * 2 * kWave + kWave + j;
+    // fragments of a block: BF16 x 3 two uint4 per lane (2 kWave per block),
+    // FP16 x 2 one (kWave per block)
+    constexpr int kStride = F16 ? kWave : 2 * kWave;
+    const uint4* __restrict__ ap0 = a.apack + pd.apack_off + (c0 / kBlk) * kStride + lane;
+    const uint4* __restrict__ ap1 = a.apack + pd.apack_off + (c0 / kBlk) * kStride + kWave + j;
 
     float best[G], sec[G];   // best block minimum, and the smallest of the other blocks
     int32_t bblk[G];
@@ -259,16 +410,26 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
         bblk[g] = t0;
     }
     const auto products = [&](const uint4& f0, const uint4& f1, f32x16_t (&acc)[G]) {
-        const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, f0);
-        const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, f1);
+        if constexpr (F16) {
+            const f16x8_t a0 = __builtin_bit_cast(f16x8_t, f0);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
+            for (int g = 0; g < G; ++g) {
 #pragma unroll
-            for (int t = 0; t < 16; ++t) acc[g][t] = 0.f;
-            acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0[g], acc[g], 0, 0, 0);
+                for (int t = 0; t < 16; ++t) acc[g][t] = 0.f;
+                acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, e0[g], acc[g], 0, 0, 0);
+            }
+        } else {
+            const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, f0);
+            const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, f1);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+#pragma unroll
+                for (int t = 0; t < 16; ++t) acc[g][t] = 0.f;
+                acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0[g], acc[g], 0, 0, 0);
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1[g], acc[g], 0, 0, 0);
         }
-#pragma unroll
-        for (int g = 0; g < G; ++g) acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1[g], acc[g], 0, 0, 0);
     };
     // minimum of the lane's sixteen values of block blk; the new second
     // smallest block minimum is the median of (best, sec, mn) as best <= sec
@@ -292,8 +453,9 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     // load touches 512 bytes instead of 1 KB.
     const auto frag = [&](int32_t blk, uint4& f0, uint4& f1) {
         const int32_t b = min(blk, t1 - 1);
-        f0 = ap0[(int64_t)b * 2 * kWave];
-        f1 = ap1[(int64_t)b * 2 * kWave];
+        f0 = ap0[(int64_t)b * kStride];
+        if constexpr (F16) f1 = f0;   // unused
+        else f1 = ap1[(int64_t)b * kStride];
     };
     if constexpr (G >= 4) {
         // Software pipeline: the products of block b are issued before the
@@ -423,8 +585,18 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
                 // distance): that norm, when below R, bounds the error
                 const double rmax = fmin((double)pd.c0[3], qn + sqrt((double)fwg));
                 const double span = (qn + rmax) * (1.0 + 0x1.0p-20);
-                const double margin = 32.0 * u * span * span;
-                fail = !((double)sec[g] - margin > (double)fwg * (1.0 + 8.0 * u));
+                if constexpr (F16) {
+                    // in scaled units: S and the bound carry 4^sexp, the
+                    // absolute term of the bound is added there
+                    const double s1 = ldexp(1.0, pd.sexp);
+                    const double sp = span * s1;
+                    const double margin = 40.0 * u * sp * sp + 0x1.0p-22 * (sp + 1.0);
+                    fail = ((far_q >> g) & 1u) != 0u ||
+                           !((double)sec[g] - margin > (double)fwg * (s1 * s1) * (1.0 + 8.0 * u));
+                } else {
+                    const double margin = 32.0 * u * span * span;
+                    fail = !((double)sec[g] - margin > (double)fwg * (1.0 + 8.0 * u));
+                }
             }
             unsigned long long mask = __ballot(fail);
             if (mask != 0ull && a.rescans != nullptr && lane == 0)
@@ -455,11 +627,11 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     __syncthreads();
 }
 
-template <int Q, int W>
+template <int Q, int W, int FMT>
 __global__ __launch_bounds__(kWave * W, (Q == 1 && W == 8) ? 4 : 1) void nn_bf16_kernel(NNBf16Args a)
 {
     __shared__ uint64_t sk[W][kWave * Q];
-    for (int64_t it = blockIdx.x; it < a.nwork; it += gridDim.x) nn_bf16_item<Q, W>(a, a.work[it], sk);
+    for (int64_t it = blockIdx.x; it < a.nwork; it += gridDim.x) nn_bf16_item<Q, W, FMT>(a, a.work[it], sk);
 }
 
 }  // namespace sicp

@@ -9,6 +9,11 @@
 
 namespace sicp {
 
+// Screen formats: three BF16 parts, two 32 x 32 x 16 products per block of
+// 32 references; or two FP16 parts of scaled coordinates, one product.
+constexpr int kFmtBf16x3 = 0;
+constexpr int kFmtF16x2 = 1;
+
 struct NNBf16Args {
     const WorkItem* work;
     const PairDesc* pairs;
@@ -24,8 +29,13 @@ struct NNBf16Args {
 // wavefronts per workgroup (4, 8, 16 for one query per lane; 4, 8 for two).
 bool nn_bf16_shape_ok(int q, int w);
 
-// q, w as above, grid workgroups (grid < nwork makes them persistent).
-hipError_t launch_nn_bf16_kernel(int q, int w, unsigned grid, const NNBf16Args& a, hipStream_t s);
+// q, w as above; fmt: 0 the BF16 x 3 screen, 1 the FP16 x 2 screen; grid
+// workgroups (grid < nwork makes them persistent).
+hipError_t launch_nn_bf16_kernel(int q, int w, int fmt, unsigned grid, const NNBf16Args& a, hipStream_t s);
+
+// FP16 screen scale exponent for a largest centred norm R (host copy of the
+// device rule).
+int f16_screen_exponent_host(float R);
 
 // The screen's centre c0 of one pair from its n_ref packed references, on
 // the device (written into pair->c0).
@@ -34,6 +44,6 @@ hipError_t launch_bf16_centre(PairDesc* pair, const float4* ref4, int64_t n_ref,
 // A fragments of the centred references of every pair; grid covers the
 // largest pair's 16-reference blocks.
 hipError_t launch_pack_bf16(const PairDesc* pairs, int32_t n_pairs, int64_t max_blocks, const float4* ref4,
-                            uint4* apack, hipStream_t s);
+                            uint4* apack, int fmt, hipStream_t s);
 
 }  // namespace sicp

@@ -63,8 +63,13 @@ void bf16_centre(const float* xyz, int64_t n, PairDesc& pd)
         r2 = std::max(r2, q);
     }
     pd.c0[3] = std::nextafter((float)(std::sqrt(r2) * (1.0 + 0x1.0p-20)), INFINITY);
+    pd.sexp = f16_screen_exponent_host(pd.c0[3]);
 }
 inline int64_t ceil_div(int64_t v, int64_t a) { return (v + a - 1) / a; }
+// The two certified matrix-core screens (BF16 x 3, FP16 x 2) against the
+// plain FP32 search.
+inline bool is_screen(int32_t mode) { return mode == STEIN_ICP_NN_BF16_RERANK || mode == STEIN_ICP_NN_F16_RERANK; }
+inline int screen_fmt(int32_t mode) { return mode == STEIN_ICP_NN_F16_RERANK ? kFmtF16x2 : kFmtBf16x3; }
 inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 // ------------------------------------------------------------------ host RNG
@@ -247,7 +252,7 @@ int validate_config(const stein_icp_config* c)
         return fail(STEIN_ICP_E_INVALID, "init half widths must be finite and >= 0");
     for (int i = 0; i < 6; ++i)
         if (!std::isfinite(c->init_centre[i])) return fail(STEIN_ICP_E_INVALID, "init_centre must be finite");
-    if (c->nn_mode != STEIN_ICP_NN_FP32 && c->nn_mode != STEIN_ICP_NN_BF16_RERANK)
+    if (c->nn_mode != STEIN_ICP_NN_FP32 && !is_screen(c->nn_mode))
         return fail(STEIN_ICP_E_INVALID, "unknown nn_mode");
     if (c->optimizer != STEIN_ICP_OPT_ADAM && c->optimizer != STEIN_ICP_OPT_SGD)
         return fail(STEIN_ICP_E_INVALID, "unknown optimizer");
@@ -294,13 +299,13 @@ void launch_nn_q(int w, unsigned nwork, const NNArgs& a, hipStream_t s)
 }
 
 // BF16 screen + FP32 rerank with the same work table and key format.
-hipError_t launch_nn_bf16(const Tiling& t, unsigned nwork, NNBf16Args a, hipStream_t s)
+hipError_t launch_nn_bf16(const Tiling& t, unsigned nwork, NNBf16Args a, int fmt, hipStream_t s)
 {
     if (nwork == 0) return hipSuccess;
     if (t.w != 4 && t.w != 8 && t.w != 16) return hipErrorInvalidValue;
     a.nwork = nwork;
     const unsigned grid = t.persist > 0 ? std::min<unsigned>(nwork, (unsigned)(t.persist * g_num_cus)) : nwork;
-    return launch_nn_bf16_kernel(t.q, t.w, grid, a, s);
+    return launch_nn_bf16_kernel(t.q, t.w, fmt, grid, a, s);
 }
 
 hipError_t launch_nn(const Tiling& t, unsigned nwork, NNArgs a, hipStream_t s)
@@ -371,7 +376,7 @@ void build_work(stein_icp_ctx* c)
 // chunk (min(waves, blocks)).
 int64_t certificates_per_launch(const stein_icp_ctx* c)
 {
-    if (c->cfg.nn_mode != STEIN_ICP_NN_BF16_RERANK) return 0;
+    if (!is_screen(c->cfg.nn_mode)) return 0;
     int64_t n = 0;
     for (const auto& g : c->groups)
         for (int32_t ch = 0; ch < g.chunks; ++ch) {
@@ -460,7 +465,7 @@ hipError_t enqueue_queries(const stein_icp_ctx* c, hipStream_t s)
 hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
 {
     if (stage == 0) {
-        if (c->cfg.nn_mode == STEIN_ICP_NN_BF16_RERANK) {
+        if (is_screen(c->cfg.nn_mode)) {
             NNBf16Args b{};
             b.work = c->d_work;
             b.pairs = c->d_groups;
@@ -469,7 +474,7 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
             b.queries = c->queries;
             b.partial = c->partial;
             b.rescans = c->rescans;
-            return launch_nn_bf16(c->tiling, (unsigned)c->work.size(), b, s);
+            return launch_nn_bf16(c->tiling, (unsigned)c->work.size(), b, screen_fmt(c->cfg.nn_mode), s);
         }
         return launch_nn(c->tiling, (unsigned)c->work.size(), nn_args(c), s);
     }
@@ -489,7 +494,7 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
     g.K = c->K;
     g.m = c->m;
     g.rows = c->rows;
-    g.index_keys = c->cfg.nn_mode == STEIN_ICP_NN_BF16_RERANK ? 1 : 0;
+    g.index_keys = is_screen(c->cfg.nn_mode) ? 1 : 0;
     const int32_t bw_pairs = const_bandwidth(c->cfg) ? 0 : c->P;
     const int64_t blocks = 2 * (int64_t)bw_pairs + ceil_div((int64_t)c->P * c->K, kGradGroups);
     hipLaunchKernelGGL(grad_bandwidth_kernel, dim3((unsigned)blocks), dim3(kSvgdThreads), grad_bw_lds_bytes(c->K), s,
@@ -618,7 +623,7 @@ int autotune(stein_icp_ctx* c, hipStream_t s)
     double best = 1e30;
     Tiling best_t = c->tiling;
     std::set<std::vector<int32_t>> seen;
-    const bool bf16 = c->cfg.nn_mode == STEIN_ICP_NN_BF16_RERANK;
+    const bool bf16 = is_screen(c->cfg.nn_mode);
     for (int q : {1, 2, 4})
         for (int w : {4, 8, 16})
             for (int64_t pw : {64, 128, 256, 512, 1024, 2048, 4096}) {
@@ -820,7 +825,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
         c->pairs.push_back(pd);
     }
     c->tiling = default_tiling(c->pairs, nq);
-    if (cfg->nn_mode == STEIN_ICP_NN_BF16_RERANK && c->tiling.q > 2) c->tiling.q = 2;
+    if (is_screen(cfg->nn_mode) && c->tiling.q > 2) c->tiling.q = 2;
     {
         // the attribute is a per-kernel ceiling shared by every context: use
         // the largest any particle count needs (the launch sizes the rest)
@@ -829,7 +834,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
         HIP_TRY(hipFuncSetAttribute((const void*)grad_bandwidth_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)most));
     }
-    const bool bf16 = cfg->nn_mode == STEIN_ICP_NN_BF16_RERANK;
+    const bool bf16 = is_screen(cfg->nn_mode);
     int64_t apack_n = 0;
     if (bf16) {
         std::vector<float> h;
@@ -838,6 +843,7 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
             if (own_ref[p] != p) {
                 const PairDesc& o = c->pairs[own_ref[p]];
                 for (int i = 0; i < 4; ++i) pd.c0[i] = o.c0[i];
+                pd.sexp = o.sexp;
                 pd.apack_off = o.apack_off;
                 continue;
             }
@@ -969,7 +975,8 @@ int init_impl(stein_icp_ctx** out, const stein_icp_config* cfg, int32_t P, const
         PairDesc* d_upairs = (PairDesc*)(c->arena + o_upairs);
         if (hipMemcpyAsync(d_upairs, uref.data(), sizeof(PairDesc) * uref.size(), hipMemcpyHostToDevice, s) !=
                 hipSuccess ||
-            launch_pack_bf16(d_upairs, (int32_t)uref.size(), maxblk, c->ref4, c->apack, s) != hipSuccess)
+            launch_pack_bf16(d_upairs, (int32_t)uref.size(), maxblk, c->ref4, c->apack, screen_fmt(cfg->nn_mode), s) !=
+                hipSuccess)
             return bail(fail(STEIN_ICP_E_DEVICE, "BF16 packing launch failed"));
     }
     int flag = 0;
@@ -1199,8 +1206,8 @@ int stein_icp_set_nn_tiling(stein_icp_ctx* ctx, int32_t qpl, int32_t waves, int3
     if (waves != 4 && waves != 8 && waves != 16) return fail(STEIN_ICP_E_INVALID, "waves must be 4, 8 or 16");
     if (chunk < kRefPad || chunk % kRefPad != 0)
         return fail(STEIN_ICP_E_INVALID, "chunk must be a positive multiple of 32");
-    if (ctx->cfg.nn_mode == STEIN_ICP_NN_BF16_RERANK && !nn_bf16_shape_ok(qpl, waves))
-        return fail(STEIN_ICP_E_INVALID, "the BF16 screen takes 1 or 2 queries per lane, and 4 or 8 waves with 2");
+    if (is_screen(ctx->cfg.nn_mode) && !nn_bf16_shape_ok(qpl, waves))
+        return fail(STEIN_ICP_E_INVALID, "the matrix-core screens take 1 or 2 queries per lane, and 4 or 8 waves with 2");
     Tiling t;
     t.q = qpl;
     t.w = waves;
@@ -1297,7 +1304,7 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
 {
     if (nq < 0 || n_ref < 1) return fail(STEIN_ICP_E_INVALID, "need nq >= 0 and n_ref >= 1");
     if (nq > kMaxRef || n_ref > kMaxRef) return fail(STEIN_ICP_E_INVALID, "sizes must be below 2^31 - 64");
-    if (mode != STEIN_ICP_NN_FP32 && mode != STEIN_ICP_NN_BF16_RERANK) return fail(STEIN_ICP_E_INVALID, "unknown nn mode");
+    if (mode != STEIN_ICP_NN_FP32 && !is_screen(mode)) return fail(STEIN_ICP_E_INVALID, "unknown nn mode");
     if (nq == 0) return STEIN_ICP_OK;
     if (!q_xyz || !ref_xyz || !idx) return fail(STEIN_ICP_E_INVALID, "a pointer is NULL");
     hipStream_t s = (hipStream_t)hip_stream;
@@ -1307,7 +1314,7 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     pd.part_stride = nq;
     pd.n_ref = n_ref;
     pd.n_ref_pad = round_up(n_ref, kRefPad);
-    const bool bf16 = mode == STEIN_ICP_NN_BF16_RERANK;
+    const bool bf16 = is_screen(mode);
     if (bf16) {
         std::vector<float> h((size_t)n_ref * 3);
         if (hipMemcpy(h.data(), ref_xyz, 12 * (size_t)n_ref, hipMemcpyDeviceToHost) != hipSuccess)
@@ -1363,7 +1370,7 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     if (e == hipSuccess && flag) rc = fail(STEIN_ICP_E_INVALID, "a coordinate is non-finite or above 1e9");
     if (e == hipSuccess && !rc) {
         if (bf16) {
-            e = launch_pack_bf16(a.pairs, 1, pd.n_ref_pad / kRefPad, a.ref4, (uint4*)(mem + o_ap), s);
+            e = launch_pack_bf16(a.pairs, 1, pd.n_ref_pad / kRefPad, a.ref4, (uint4*)(mem + o_ap), screen_fmt(mode), s);
             NNBf16Args b{};
             b.work = a.work;
             b.pairs = a.pairs;
@@ -1371,7 +1378,7 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
             b.apack = (const uint4*)(mem + o_ap);
             b.queries = a.queries;
             b.partial = a.partial;
-            if (e == hipSuccess) e = launch_nn_bf16(t, (unsigned)work.size(), b, s);
+            if (e == hipSuccess) e = launch_nn_bf16(t, (unsigned)work.size(), b, screen_fmt(mode), s);
         } else {
             e = launch_nn(t, (unsigned)work.size(), a, s);
         }
@@ -1440,10 +1447,10 @@ int stein_icp_nn_noalloc(const float* q_xyz, int64_t nq, const float* ref_xyz, i
 {
     if (nq < 0 || n_ref < 1) return fail(STEIN_ICP_E_INVALID, "need nq >= 0 and n_ref >= 1");
     if (nq > kMaxRef || n_ref > kMaxRef) return fail(STEIN_ICP_E_INVALID, "sizes must be below 2^31 - 64");
-    if (mode != STEIN_ICP_NN_FP32 && mode != STEIN_ICP_NN_BF16_RERANK) return fail(STEIN_ICP_E_INVALID, "unknown nn mode");
+    if (mode != STEIN_ICP_NN_FP32 && !is_screen(mode)) return fail(STEIN_ICP_E_INVALID, "unknown nn mode");
     if (nq == 0) return STEIN_ICP_OK;
     if (!q_xyz || !ref_xyz || !idx) return fail(STEIN_ICP_E_INVALID, "a pointer is NULL");
-    const bool bf16 = mode == STEIN_ICP_NN_BF16_RERANK;
+    const bool bf16 = is_screen(mode);
     PairDesc pd{};
     pd.nq = nq;
     pd.part_stride = nq;
@@ -1504,7 +1511,7 @@ int stein_icp_nn_noalloc(const float* q_xyz, int64_t nq, const float* ref_xyz, i
     if (flag) return fail(STEIN_ICP_E_INVALID, "a coordinate is non-finite or above 1e9");
     if (bf16) {
         e = launch_bf16_centre(d_pd, r4, n_ref, s);
-        if (e == hipSuccess) e = launch_pack_bf16(d_pd, 1, pd.n_ref_pad / kRefPad, r4, ap, s);
+        if (e == hipSuccess) e = launch_pack_bf16(d_pd, 1, pd.n_ref_pad / kRefPad, r4, ap, screen_fmt(mode), s);
         NNBf16Args b{};
         b.work = work;
         b.pairs = d_pd;
@@ -1512,7 +1519,7 @@ int stein_icp_nn_noalloc(const float* q_xyz, int64_t nq, const float* ref_xyz, i
         b.apack = ap;
         b.queries = q4;
         b.partial = keys;
-        if (e == hipSuccess) e = launch_nn_bf16(t, (unsigned)nwork, b, s);
+        if (e == hipSuccess) e = launch_nn_bf16(t, (unsigned)nwork, b, screen_fmt(mode), s);
     } else {
         NNArgs a{};
         a.work = work;

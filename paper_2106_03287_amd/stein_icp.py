@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libstein_icp.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE = 0, -1, -2, -3, -4
-NN_FP32, NN_BF16_RERANK = 0, 1
+NN_FP32, NN_BF16_RERANK, NN_F16_RERANK = 0, 1, 2
 OPT_ADAM, OPT_SGD = 0, 1
 BW_MEDIAN, BW_FIXED = 0, 1
 PRIOR_UNIFORM, PRIOR_GAUSS_VONMISES = 0, 1

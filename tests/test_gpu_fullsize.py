@@ -43,18 +43,18 @@ def _assert_step(diag, th_gpu, od, th_or, tag):
 
 
 def test_lidar_iterations_late_in_the_solve_at_the_bench_shapes():
-    """LiDAR (K 300, m 1000, M 100,000, T 300) solved on the GPU with both
-    searches at the NN shapes the bench times; at t = 50, 150 and 299 the
-    two GPU states are bitwise equal, and the next iteration from that state
-    matches the oracle's. The BF16 screen's failed certificates (rescanned
-    in FP32) are counted along the way."""
+    """LiDAR (K 300, m 1000, M 100,000, T 300) solved on the GPU with the
+    FP32 search and both matrix-core screens at the NN shapes the bench
+    times; at t = 50, 150 and 299 the three GPU states are bitwise equal, and
+    the next iteration from that state matches the oracle's. The screens' failed certificates (rescanned in
+    FP32) are counted along the way."""
     prob = synth.make_problem("lidar", 0)
     rows = prob.schedule.shape[0]
     cfg = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m, schedule_rows=rows, lr=prob.lr)
     ocfg = oracle.make_config(prob.K, prob.m, len(prob.pair.src), len(prob.pair.ref), lr=prob.lr)
     src, ref, th0, sch = dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule)
     sols = {}
-    for nn, mode in (("fp32", S.NN_FP32), ("bf16", S.NN_BF16_RERANK)):
+    for nn, mode in (("fp32", S.NN_FP32), ("bf16", S.NN_BF16_RERANK), ("f16", S.NN_F16_RERANK)):
         cfg.nn_mode = mode
         sols[nn] = S.SteinICP(cfg, src, ref, th0, sch)
         sols[nn].set_tiling(*_pinned("lidar", nn))
@@ -65,8 +65,9 @@ def test_lidar_iterations_late_in_the_solve_at_the_bench_shapes():
             for sol in sols.values():
                 sol.step(t - done)
             states = {nn: sol.get_state() for nn, sol in sols.items()}
-            for a, b in zip(states["fp32"][:3], states["bf16"][:3]):
-                assert torch.equal(a, b)
+            for other in ("bf16", "f16"):
+                for a, b in zip(states["fp32"][:3], states[other][:3]):
+                    assert torch.equal(a, b)
             th, mo, ve, tt = states["fp32"]
             assert tt == t
             st = oracle.State(th.cpu().numpy()[0], mo.cpu().numpy()[0], ve.cpu().numpy()[0], t)
@@ -76,9 +77,11 @@ def test_lidar_iterations_late_in_the_solve_at_the_bench_shapes():
                 sol.step(1)
                 diag = {k: v.cpu().numpy()[0] for k, v in sol.diagnostics().items()}
                 _assert_step(diag, sol.particles().cpu().numpy()[0], od, st.theta, f"lidar {nn} t={t}")
-            r, n = sols["bf16"].nn_rescans()
-            print(f"lidar t={t + 1}: BF16 certificates {n}, failed and rescanned {r} ({r / n:.2e})", flush=True)
-            assert 0 < n and 0 <= r < n
+            for other in ("bf16", "f16"):
+                r, n = sols[other].nn_rescans()
+                print(f"lidar t={t + 1}: {other} certificates {n}, failed and rescanned {r} ({r / n:.2e})",
+                      flush=True)
+                assert 0 < n and 0 <= r < n
             done = t + 1
         assert sols["fp32"].nn_rescans() == (0, 0)
     finally:
@@ -92,9 +95,10 @@ def batched64():
     return synth.batched_problems(64)
 
 
-def test_batched_64_full_size_pairs_equal_sequential_solves_and_the_oracle(batched64):
+@pytest.mark.parametrize("mode", [S.NN_BF16_RERANK, S.NN_F16_RERANK])
+def test_batched_64_full_size_pairs_equal_sequential_solves_and_the_oracle(batched64, mode):
     """The batched workload at full size (64 pairs, M 2k-50k, N 1k-20k, K 100,
-    m 300, T 150) in one context with the certified BF16 search at the
+    m 300, T 150) in one context with a certified matrix-core screen at the
     tuner's shapes equals 64 single-pair FP32 contexts bit for bit after
     the whole solve; the first and the last-plus-one iterations of three
     pairs (the largest reference among them) match the oracle."""
@@ -107,7 +111,7 @@ def test_batched_64_full_size_pairs_equal_sequential_solves_and_the_oracle(batch
     scheds = [dev(p.schedule) for p in probs]
     th0 = dev(np.stack([p.theta0 for p in probs]))
     cfg = S.stein_icp_default_config(num_particles=K, batch_size=m, schedule_rows=rows, lr=probs[0].lr,
-                                     nn_mode=S.NN_BF16_RERANK, autotune=1)
+                                     nn_mode=mode, autotune=1)
     print(f"batched: {P} pairs, M {min(len(p.pair.ref) for p in probs)}-{max(len(p.pair.ref) for p in probs)}",
           flush=True)
     batch = S.SteinICP.batch(cfg, srcs, refs, th0, scheds)
@@ -145,6 +149,6 @@ def test_batched_64_full_size_pairs_equal_sequential_solves_and_the_oracle(batch
             od = oracle.step(ocfgs[i], probs[i].pair.src, probs[i].pair.ref, probs[i].schedule[T % rows], st)
             _assert_step({k: v[i] for k, v in diag.items()}, th[i], od, st.theta, f"pair {i} t={T}")
         r, n = batch.nn_rescans()
-        print(f"batched: BF16 certificates {n}, failed and rescanned {r} ({r / n:.2e})", flush=True)
+        print(f"batched (mode {mode}): certificates {n}, failed and rescanned {r} ({r / n:.2e})", flush=True)
     finally:
         batch.close()

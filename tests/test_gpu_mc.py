@@ -61,14 +61,15 @@ def oracle_runs(mc, T, idx):
     return np.array(out)
 
 
-@pytest.mark.parametrize("extra", [{}, {"nn_mode": S.NN_BF16_RERANK}, {"metric": S.METRIC_PLANE}])
+@pytest.mark.parametrize("extra", [{}, {"nn_mode": S.NN_BF16_RERANK}, {"nn_mode": S.NN_F16_RERANK},
+                                   {"metric": S.METRIC_PLANE}])
 def test_shared_clouds_equal_separate_copies_bitwise(extra):
     mc = synth.mc_problem("cuboid", 0, runs=24, T=30, half_trans=0.2, half_rot=0.5)
     print(f"mc shared vs copies: {extra}", flush=True)
     a = run(mc, 30, shared=True, **extra)
     b = run(mc, 30, shared=False, **extra)
     np.testing.assert_array_equal(a, b)
-    if extra.get("nn_mode") == S.NN_BF16_RERANK:
+    if extra.get("nn_mode") in (S.NN_BF16_RERANK, S.NN_F16_RERANK):
         np.testing.assert_array_equal(a, run(mc, 30, shared=True))
 
 

@@ -425,57 +425,66 @@ def test_batched_uneven_pairs_tuned_and_persistent():
 
 # ------------------------------------------------------------------ BF16 screen + FP32 rerank
 
-def _bf16_check(q, ref):
-    """The certified BF16 screen returns the FP32 search's answer: the same
-    index (lowest on ties) and the same FP32 distance, bit for bit."""
-    idx, d2 = S.stein_icp_nn(dev(q), dev(ref), mode=S.NN_BF16_RERANK)
+SCREENS = [S.NN_BF16_RERANK, S.NN_F16_RERANK]
+
+
+def _bf16_check(q, ref, mode=S.NN_BF16_RERANK):
+    """A certified matrix-core screen (BF16 x 3 or FP16 x 2) returns the FP32
+    search's answer: the same index (lowest on ties) and the same FP32
+    distance, bit for bit."""
+    idx, d2 = S.stein_icp_nn(dev(q), dev(ref), mode=mode)
     idx, d2 = idx.cpu().numpy(), d2.cpu().numpy()
     oi, od = oracle.nn_f32(q, ref)
     np.testing.assert_array_equal(idx, oi)
     np.testing.assert_array_equal(d2.view(np.uint32), od.astype(np.float32).view(np.uint32))
 
 
-def test_bf16_screen_kinect_queries():
+@pytest.mark.parametrize("mode", SCREENS)
+def test_bf16_screen_kinect_queries(mode):
     prob = synth.make_problem("kinect", 0, T=1)
     rng = np.random.default_rng(8)
     sel = rng.choice(len(prob.pair.src), 4000, replace=False)
     q = np.concatenate([oracle.transform(prob.theta0[k], prob.pair.src[sel[k::8]]) for k in range(8)])
-    _bf16_check(q.astype(np.float32), prob.pair.ref)
+    _bf16_check(q.astype(np.float32), prob.pair.ref, mode)
 
 
-def test_bf16_screen_lidar_queries():
+@pytest.mark.parametrize("mode", SCREENS)
+def test_bf16_screen_lidar_queries(mode):
     # 80 m coordinates: the error bound is wide and many queries take the
     # exact FP32 path; the answers must still be the FP32 search's
     prob = synth.make_problem("lidar", 0, K=1, T=1)
     rng = np.random.default_rng(9)
     sel = rng.choice(len(prob.pair.src), 3000, replace=False)
     q = oracle.transform(prob.theta0[0], prob.pair.src[sel]).astype(np.float32)
-    _bf16_check(q, prob.pair.ref)
+    _bf16_check(q, prob.pair.ref, mode)
 
 
+@pytest.mark.parametrize("mode", SCREENS)
 @pytest.mark.parametrize("nq,M", [(1, 1), (100, 17), (4097, 2000), (0, 5)])
-def test_bf16_screen_ragged_sizes(nq, M):
+def test_bf16_screen_ragged_sizes(nq, M, mode):
     rng = np.random.default_rng(nq + 7 * M)
     ref = rng.uniform(-1, 1, (M, 3)).astype(np.float32)
     q = rng.uniform(-1.2, 1.2, (nq, 3)).astype(np.float32)
     if nq == 0:
-        S.stein_icp_nn(dev(q).reshape(-1, 3), dev(ref), mode=S.NN_BF16_RERANK)
+        S.stein_icp_nn(dev(q).reshape(-1, 3), dev(ref), mode=mode)
         return
-    _bf16_check(q, ref)
+    _bf16_check(q, ref, mode)
 
 
-def test_bf16_screen_exact_ties_go_to_the_lowest_index():
+@pytest.mark.parametrize("mode", SCREENS)
+def test_bf16_screen_exact_ties_go_to_the_lowest_index(mode):
     # points on an integer grid, references repeated: many exact ties,
     # within and across 16-reference blocks and screen lanes
     rng = np.random.default_rng(31)
     base = rng.integers(-6, 7, (700, 3)).astype(np.float32)
     ref = np.concatenate([base, base[::-1], base[rng.permutation(700)]])
     q = (rng.integers(-12, 13, (3000, 3)) / 2.0).astype(np.float32)
-    _bf16_check(q, ref)
+    _bf16_check(q, ref, mode)
 
 
+@pytest.mark.parametrize("mode", SCREENS)
 @pytest.mark.parametrize("seed", range(16))
-def test_bf16_screen_randomized_scales_offsets_and_near_ties(seed):
+def test_bf16_screen_randomized_scales_offsets_and_near_ties(seed, mode):
     """The certificate's error bound scales with the centred norms, so the
     screen is swept over cloud scales from 0.1 m to 100 m, centres up to
     300 m from the origin, near-duplicate references (jittered copies) and
@@ -491,7 +500,7 @@ def test_bf16_screen_randomized_scales_offsets_and_near_ties(seed):
     ref[dup[: len(dup) // 2]] = ref[dup[len(dup) // 2:2 * (len(dup) // 2)]] + rng.normal(0, 1e-6 * scale, (len(dup) // 2, 3))
     near = rng.choice(M, nq, replace=True)
     q = ref[near] + rng.normal(0, 1e-3 * scale, (nq, 3)) * rng.uniform(0, 1, (nq, 1))
-    _bf16_check(q.astype(np.float32), ref.astype(np.float32))
+    _bf16_check(q.astype(np.float32), ref.astype(np.float32), mode)
 
 
 def _grid_problem():
@@ -508,9 +517,10 @@ def _grid_problem():
     return src, ref, theta0, sched, K, m, rows
 
 
+@pytest.mark.parametrize("mode", SCREENS)
 @pytest.mark.parametrize("q", [1, 2])
 @pytest.mark.parametrize("w", [4, 8, 16])
-def test_bf16_screen_every_block_count_per_wavefront(q, w):
+def test_bf16_screen_every_block_count_per_wavefront(q, w, mode):
     """Chunks of 1 to 89 blocks of 32 references give the wavefronts of a
     workgroup 0 to 22 blocks each: every trip count of the screen's block
     loops (the two-buffer loop and the software pipeline, both tails) and
@@ -523,7 +533,7 @@ def test_bf16_screen_every_block_count_per_wavefront(q, w):
         # not built (two queries per lane need more registers than sixteen
         # wavefronts leave): the shape is refused, nothing is launched
         cfg = S.stein_icp_default_config(num_particles=prob.K, batch_size=prob.m, schedule_rows=1,
-                                         nn_mode=S.NN_BF16_RERANK)
+                                         nn_mode=mode)
         sol = S.SteinICP(cfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule[:1]))
         try:
             with pytest.raises(S.SteinICPError):
@@ -533,7 +543,7 @@ def test_bf16_screen_every_block_count_per_wavefront(q, w):
         return
     for src, ref, theta0, sched, K, m, rows in cases:
         cfg = S.stein_icp_default_config(num_particles=K, batch_size=m, schedule_rows=rows, autotune=0,
-                                         nn_mode=S.NN_BF16_RERANK)
+                                         nn_mode=mode)
         ocfg = oracle.make_config(K, m, len(src), len(ref))
         want = oracle.step(ocfg, src, ref, sched[0], oracle.State(theta0))["match"]
         sol = S.SteinICP(cfg, dev(src), dev(ref), dev(theta0), dev(sched))
@@ -554,7 +564,7 @@ def test_bf16_solver_equals_the_fp32_solver_bitwise():
         prob = synth.make_problem(name, 0, T=10)
         gcfg, ocfg = both_configs(prob, {})
         runs = {}
-        for mode in (S.NN_FP32, S.NN_BF16_RERANK):
+        for mode in (S.NN_FP32, S.NN_BF16_RERANK, S.NN_F16_RERANK):
             gcfg.nn_mode = mode
             sol = S.SteinICP(gcfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule))
             sol.step(1)
@@ -567,6 +577,8 @@ def test_bf16_solver_equals_the_fp32_solver_bitwise():
         np.testing.assert_array_equal(runs[S.NN_BF16_RERANK][0], od["match"])
         np.testing.assert_array_equal(runs[S.NN_BF16_RERANK][0], runs[S.NN_FP32][0])
         np.testing.assert_array_equal(runs[S.NN_BF16_RERANK][1], runs[S.NN_FP32][1])
+        np.testing.assert_array_equal(runs[S.NN_F16_RERANK][0], od["match"])
+        np.testing.assert_array_equal(runs[S.NN_F16_RERANK][1], runs[S.NN_FP32][1])
 
 
 # ------------------------------------------------------------------ the bench's launch shapes
@@ -583,7 +595,7 @@ def test_kinect_full_solve_at_the_bench_shapes_bf16_equals_fp32_and_oracle():
     prob = synth.make_problem("kinect", 0)
     print(f"kinect full solve at bench shapes: T={prob.T}", flush=True)
     out = {}
-    for nn, mode in (("bf16", S.NN_BF16_RERANK), ("fp32", S.NN_FP32)):
+    for nn, mode in (("bf16", S.NN_BF16_RERANK), ("f16", S.NN_F16_RERANK), ("fp32", S.NN_FP32)):
         gcfg, _ = both_configs(prob)
         gcfg.nn_mode = mode
         sol = S.SteinICP(gcfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule))
@@ -592,17 +604,18 @@ def test_kinect_full_solve_at_the_bench_shapes_bf16_equals_fp32_and_oracle():
         out[nn] = sol.particles().cpu().numpy()[0]
         sol.close()
     np.testing.assert_array_equal(out["bf16"], out["fp32"])
+    np.testing.assert_array_equal(out["f16"], out["fp32"])
     assert_poses_close(out["bf16"], oracle_run(prob, prob.T))
 
 
-@pytest.mark.parametrize("nn", ["bf16", "fp32"])
+@pytest.mark.parametrize("nn", ["bf16", "f16", "fp32"])
 def test_lidar_full_size_iteration_at_the_bench_shape(nn):
     """One LiDAR iteration (K 300, m 1000, M 100,000) with the pinned NN shape
     the bench times, against the oracle (matches bit-exact)."""
     prob = synth.make_problem("lidar", 0, T=1)
     print(f"lidar full-size iteration at the bench shape ({nn})", flush=True)
     gcfg, ocfg = both_configs(prob)
-    gcfg.nn_mode = S.NN_BF16_RERANK if nn == "bf16" else S.NN_FP32
+    gcfg.nn_mode = {"bf16": S.NN_BF16_RERANK, "f16": S.NN_F16_RERANK, "fp32": S.NN_FP32}[nn]
     sol = S.SteinICP(gcfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule))
     sol.set_tiling(*_pinned("lidar", nn))
     sol.step(1)
@@ -621,7 +634,7 @@ def test_batched_uneven_pairs_bf16_equals_fp32_bitwise():
     search's particles bit for bit."""
     probs = synth.batched_problems(6, K=16, m=40, T=8, size_scale=0.3)
     out = {}
-    for mode in (S.NN_FP32, S.NN_BF16_RERANK):
+    for mode in (S.NN_FP32, S.NN_BF16_RERANK, S.NN_F16_RERANK):
         gcfg, _ = both_configs(probs[0])
         gcfg.nn_mode = mode
         b = S.SteinICP.batch(gcfg, [dev(p.pair.src) for p in probs], [dev(p.pair.ref) for p in probs],
@@ -630,3 +643,4 @@ def test_batched_uneven_pairs_bf16_equals_fp32_bitwise():
         out[mode] = b.particles().cpu().numpy()
         b.close()
     np.testing.assert_array_equal(out[S.NN_BF16_RERANK], out[S.NN_FP32])
+    np.testing.assert_array_equal(out[S.NN_F16_RERANK], out[S.NN_FP32])

@@ -230,11 +230,11 @@ def test_plane_context_normals_batched_and_graphs_agree_bitwise():
         assert_poses_close(got[i], oracle_run(p, 6))
 
 
-def test_plane_with_the_certified_bf16_search_equals_fp32_bitwise():
+def test_plane_with_the_certified_screens_equals_fp32_bitwise():
     prob = synth.make_problem("kinect", 2, T=30)
     a = gpu_run(prob, 30)
-    b = gpu_run(prob, 30, nn_mode=S.NN_BF16_RERANK)
-    np.testing.assert_array_equal(a, b)
+    for mode in (S.NN_BF16_RERANK, S.NN_F16_RERANK):
+        np.testing.assert_array_equal(a, gpu_run(prob, 30, nn_mode=mode))
 
 
 def test_point_to_point_context_holds_no_normals():

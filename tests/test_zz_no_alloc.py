@@ -24,7 +24,7 @@ def _cloud(seed, nq, M, scale, centre):
     return q.astype(np.float32), ref.astype(np.float32)
 
 
-@pytest.mark.parametrize("mode", [S.NN_FP32, S.NN_BF16_RERANK])
+@pytest.mark.parametrize("mode", [S.NN_FP32, S.NN_BF16_RERANK, S.NN_F16_RERANK])
 def test_noalloc_search_equals_the_allocating_search_on_two_calls(mode):
     cases = [_cloud(1, 30000, 20011, 0.5, np.array([0.3, -0.2, 1.0])),    # larger first
              _cloud(2, 777, 1000, 20.0, np.array([40.0, 5.0, -3.0]))]     # then smaller
