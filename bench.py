@@ -41,11 +41,12 @@ NN_SOURCES = ["paper_2106_03287_amd/csrc/nn.hpp", "paper_2106_03287_amd/csrc/com
 NN_BF16_SOURCES = NN_SOURCES + ["paper_2106_03287_amd/csrc/nn_bf16.hpp"]
 
 
-def host_info():
+def host_info(smi=True):
     """Host CPU and the GPU's clocks and power as found (rocm-smi, run as a
     child process). Called before this process touches the GPU: a process
-    that has initialised the GPU starts no other program. Any field that
-    cannot be read is None."""
+    that has initialised the GPU starts no other program (under a profiler
+    that initialises it first, pass --no-smi). Any field that cannot be read
+    is None."""
     import subprocess
     info = {"cpu_model": None, "cpu_threads": os.cpu_count(), "rocm_smi": None}
     try:
@@ -57,6 +58,8 @@ def host_info():
     except OSError:
         pass
     try:
+        if not smi:
+            raise RuntimeError("rocm-smi not queried")
         r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--json"], capture_output=True, text=True,
                            timeout=20)
         card = next(iter(json.loads(r.stdout).values()))
@@ -196,6 +199,9 @@ def main():
     ap.add_argument("--metric", default="point", choices=["point", "plane"],
                     help="ICP error metric: point-to-point (Eqs. 4-5) or point-to-plane (normals at init)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-smi", action="store_true",
+                    help="do not query rocm-smi (a profiler that initialises the GPU before the program starts "
+                         "forbids starting another program)")
     ap.add_argument("--autotune", type=int, default=0,
                     help="tune the NN shape at init instead of using the pinned shape of the workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -210,7 +216,7 @@ def main():
               "(the particle-sharded multi-GPU design is described, not built)", file=sys.stderr)
         sys.exit(2)
 
-    args.host = host_info()   # before anything touches the GPU
+    args.host = host_info(not args.no_smi)   # before anything touches the GPU
     import torch
     import synth
     from paper_2106_03287_amd import stein_icp as S
