@@ -252,6 +252,24 @@ const char *stein_icp_last_error(void);
 int stein_icp_nn(const float *q_xyz, int64_t nq, const float *ref_xyz, int64_t n_ref,
                  int32_t mode, int32_t *idx, float *d2, void *hip_stream);
 
+/* The raw screened values of a matrix-core screen, for checking its error
+ * bound: for mode BF16_RERANK or F16_RERANK, values[i * n_ref + j] (device
+ * FP32, nq x n_ref, nq * n_ref <= 2^31) is |q_i|^2 + |r_j|^2 - 2 q_i.r_j as
+ * that screen computes it (centred on the reference centroid, split into
+ * BF16 or FP16 parts, on the same matrix products; the FP16 screen's values
+ * are divided by 4^scale_exp, exactly), NaN for a query the FP16 screen
+ * does not screen. centre (host, 4 floats, may be NULL): the centroid
+ * c0[0..2] and the bound R >= every centred reference norm; scale_exp
+ * (host, may be NULL): the FP16 screen's power-of-two scale. The error
+ * bounds: |S - F| <= 52 u (|q_c| + R)^2 + 6.2 u F (BF16 x 3) and
+ * |S - F| <= 50 u (|q_c| + |r_c|)^2 + 2^-22 (|q_c| + |r_c| + 2^-e) 2^-e
+ * with e = scale_exp (FP16 x 2), u = 2^-24, F the FP32 squared distance of
+ * Eq. 1, allowing the matrix core up to one FP32 ulp of its partial sum per
+ * addition. Allocates and frees its own scratch; blocking. */
+int stein_icp_screen_values(const float *q_xyz, int64_t nq, const float *ref_xyz, int64_t n_ref,
+                            int32_t mode, float *values, float *centre, int32_t *scale_exp,
+                            void *hip_stream);
+
 /* stein_icp_nn for callers that cannot allocate device memory (code that
  * runs while a stream is being captured into a hipGraph, tight serving
  * loops, harnesses that forbid hipMalloc): the same search, arguments,

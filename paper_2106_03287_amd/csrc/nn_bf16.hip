@@ -37,6 +37,18 @@ hipError_t launch_nn_bf16_kernel(int q, int w, int fmt, unsigned grid, const NNB
 
 int f16_screen_exponent_host(float R) { return f16_screen_exponent(R); }
 
+hipError_t launch_screen_values(const PairDesc* pair, int64_t n_ref_pad, const uint4* apack, const float4* queries,
+                                int64_t nq, int fmt, float* values, hipStream_t s)
+{
+    if (nq < 1) return hipSuccess;
+    const dim3 grid((unsigned)(n_ref_pad / kBlk), (unsigned)((nq + 31) / 32));
+    if (fmt == kFmtF16x2)
+        hipLaunchKernelGGL(screen_values_kernel<kFmtF16x2>, grid, dim3(kWave), 0, s, pair, apack, queries, nq, values);
+    else
+        hipLaunchKernelGGL(screen_values_kernel<kFmtBf16x3>, grid, dim3(kWave), 0, s, pair, apack, queries, nq, values);
+    return hipGetLastError();
+}
+
 hipError_t launch_bf16_centre(PairDesc* pair, const float4* ref4, int64_t n_ref, hipStream_t s)
 {
     hipLaunchKernelGGL(bf16_centre_kernel, dim3(1), dim3(kCentreThreads), 0, s, pair, ref4, n_ref);

@@ -29,14 +29,18 @@
 //
 // Certificate: the result is the FP32 search's exact chunk minimum, ties
 // included. Let S be the screened and F the FP32 distance of a reference.
-// |S - F| <= eps = 28 u (|q_c| + R)^2 + 6.2 u F (u = 2^-24, R the pair's
-// largest centred reference norm): FP32 additions of 24 exact BF16 products
-// whose magnitudes sum to at most (|q_c| + |r_c|)^2, the dropped BF16 cross
-// terms and the FP32 norms, the FP32 centring, and the FP32 direct
-// difference. Each lane also keeps s2, the smallest block minimum of its
+// |S - F| <= eps = 52 u (|q_c| + R)^2 + 6.2 u F (u = 2^-24, R the pair's
+// largest centred reference norm): the sum of 24 exact BF16 products whose
+// magnitudes sum to at most (|q_c| + |r_c|)^2, the dropped BF16 cross terms
+// and the FP32 norms, the FP32 centring, and the FP32 direct difference. The
+// matrix core's order and rounding of its additions are not specified; the
+// sum is bounded as if each of its additions lost up to one FP32 ulp of its
+// partial sum (truncation as well as rounding to nearest), 2u of the
+// magnitudes per addition, which measured errors on stress inputs stay well
+// inside. Each lane also keeps s2, the smallest block minimum of its
 // rows outside its best block. After the workgroup merges its keys into the
 // chunk minimum F_wg, a lane whose references outside its best block all
-// satisfy F > F_wg -- guaranteed when s2 - 32 u (|q_c| + R')^2 > F_wg (1 + 8 u)
+// satisfy F > F_wg -- guaranteed when s2 - 60 u (|q_c| + R')^2 > F_wg (1 + 8 u)
 // with R' = min(R, |q_c| + sqrt(F_wg)), as only references within sqrt(F_wg)
 // of the query can win -- has lost nothing; otherwise that lane's own rows
 // of its wavefront's blocks are searched again in FP32 by the wavefront and
@@ -126,11 +130,13 @@ __device__ __forceinline__ void slot_fragments(const float c[3], bool ref, int h
 // Error (scaled units, q' and r' the scaled centred points, u = 2^-24): the
 // dropped cross parts m_q m_r, h_q rest_r, rest_q h_r, ... with the factor 2
 // give at most 24.1 u |q'||r'| + 3.5 2^-25 (|q'| + |r'|); the norms' FP32
-// rounding and split 3.1 u (|q'|^2 + |r'|^2) + 2^-24; the FP32 sum of the
-// exact products 16.1 u (|q'| + |r'|)^2; the centring 2.1 u (|q'| + |r'|)^2;
-// the FP32 direct difference of the rerank 6.2 u (|q'| + |r'|)^2. All told
-// |S - s^2 F| <= 34 u (|q'| + |r'|)^2 + 2^-22 (|q'| + |r'| + 1); the
-// certificate uses 40 u in place of 34 u. A query whose scaled centred norm
+// rounding and split 3.1 u (|q'|^2 + |r'|^2) + 2^-24; the matrix core's sum
+// of the exact products and its zero accumulator 32.1 u (|q'| + |r'|)^2 (up
+// to one FP32 ulp of the partial sum lost per addition, as for the BF16
+// screen); the centring 2.1 u (|q'| + |r'|)^2; the FP32 direct difference of
+// the rerank 6.2 u (|q'| + |r'|)^2. All told
+// |S - s^2 F| <= 50 u (|q'| + |r'|)^2 + 2^-22 (|q'| + |r'| + 1); the
+// certificate uses 56 u in place of 50 u. A query whose scaled centred norm
 // exceeds kF16QueryMax (its norm would leave FP16's comfortable range) is
 // not screened: its lanes fail the certificate and search in FP32.
 typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
@@ -590,11 +596,11 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
                     // absolute term of the bound is added there
                     const double s1 = ldexp(1.0, pd.sexp);
                     const double sp = span * s1;
-                    const double margin = 40.0 * u * sp * sp + 0x1.0p-22 * (sp + 1.0);
+                    const double margin = 56.0 * u * sp * sp + 0x1.0p-22 * (sp + 1.0);
                     fail = ((far_q >> g) & 1u) != 0u ||
                            !((double)sec[g] - margin > (double)fwg * (s1 * s1) * (1.0 + 8.0 * u));
                 } else {
-                    const double margin = 32.0 * u * span * span;
+                    const double margin = 60.0 * u * span * span;
                     fail = !((double)sec[g] - margin > (double)fwg * (1.0 + 8.0 * u));
                 }
             }
@@ -625,6 +631,66 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
         if (qi < nq) a.partial[pd.part_off + (int64_t)w.chunk * nq + qi] = sk[0][jj];
     }
     __syncthreads();
+}
+
+// The raw screened values |q|^2 + |r|^2 - 2 q.r of a screen, in the
+// units of the input (FP16 x 2: divided by 4^sexp, exactly), for checking
+// its error bound: the same fragments and matrix products as the screen.
+// grid (reference blocks of 32, query groups of 32), one wavefront each.
+// values: nq x n_ref row-major; NaN for a query the FP16 screen does not
+// screen (beyond kF16QueryMax after scaling).
+template <int FMT>
+__global__ __launch_bounds__(kWave) void screen_values_kernel(const PairDesc* __restrict__ pairs,
+                                                              const uint4* __restrict__ apack,
+                                                              const float4* __restrict__ queries, int64_t nq,
+                                                              float* __restrict__ values)
+{
+    constexpr bool F16 = FMT == kFmtF16x2;
+    const PairDesc pd = pairs[0];
+    const int lane = threadIdx.x, j = lane & 31, h = lane >> 5;
+    const int64_t blk = blockIdx.x;
+    const int64_t qi = (int64_t)blockIdx.y * 32 + j;
+    const float4 qf = qi < nq ? queries[qi] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float c[3];
+    {
+#pragma clang fp contract(off)
+        c[0] = qf.x - pd.c0[0];
+        c[1] = qf.y - pd.c0[1];
+        c[2] = qf.z - pd.c0[2];
+    }
+    f32x16_t acc;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc[t] = 0.f;
+    bool far = false;
+    if constexpr (F16) {
+        scale_coords(c, pd.sexp);
+        far = !(fabsf(c[0]) <= kF16QueryMax && fabsf(c[1]) <= kF16QueryMax && fabsf(c[2]) <= kF16QueryMax &&
+                (c[0] * c[0] + c[1] * c[1]) + c[2] * c[2] <= kF16QueryMax * kF16QueryMax);
+        if (far) c[0] = c[1] = c[2] = 0.0f;
+        u16x8_t v;
+        slot_fragment_f16(c, false, h, v);
+        const uint4 f0 = apack[pd.apack_off + blk * kWave + lane];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8_t, f0), __builtin_bit_cast(f16x8_t, v),
+                                                     acc, 0, 0, 0);
+    } else {
+        u16x8_t v0, v1;
+        slot_fragments(c, false, h, v0, v1);
+        const uint4 f0 = apack[pd.apack_off + blk * 2 * kWave + lane];
+        const uint4 f1 = apack[pd.apack_off + blk * 2 * kWave + kWave + j];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, f0), __builtin_bit_cast(bf16x8_t, v0),
+                                                      acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, f1), __builtin_bit_cast(bf16x8_t, v1),
+                                                      acc, 0, 0, 0);
+    }
+    if (qi >= nq) return;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int64_t r = blk * kBlk + blk_row(t, h);
+        if (r < pd.n_ref) {
+            const float x = F16 ? ldexpf(acc[t], -2 * pd.sexp) : acc[t];
+            values[qi * pd.n_ref + r] = far ? __builtin_nanf("") : x;
+        }
+    }
 }
 
 template <int Q, int W, int FMT>

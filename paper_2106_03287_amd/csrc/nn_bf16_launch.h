@@ -41,6 +41,11 @@ int f16_screen_exponent_host(float R);
 // the device (written into pair->c0).
 hipError_t launch_bf16_centre(PairDesc* pair, const float4* ref4, int64_t n_ref, hipStream_t s);
 
+// The raw screened values of every (query, reference) of one pair (the
+// screen's own fragments and products), nq x n_ref row-major.
+hipError_t launch_screen_values(const PairDesc* pair, int64_t n_ref_pad, const uint4* apack, const float4* queries,
+                                int64_t nq, int fmt, float* values, hipStream_t s);
+
 // A fragments of the centred references of every pair; grid covers the
 // largest pair's 16-reference blocks.
 hipError_t launch_pack_bf16(const PairDesc* pairs, int32_t n_pairs, int64_t max_blocks, const float4* ref4,

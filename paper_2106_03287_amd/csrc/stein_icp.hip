@@ -1394,6 +1394,66 @@ int stein_icp_nn(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n
     return rc;
 }
 
+int stein_icp_screen_values(const float* q_xyz, int64_t nq, const float* ref_xyz, int64_t n_ref, int32_t mode,
+                            float* values, float* centre, int32_t* scale_exp, void* hip_stream)
+{
+    if (!is_screen(mode)) return fail(STEIN_ICP_E_INVALID, "mode must be one of the matrix-core screens");
+    if (nq < 0 || n_ref < 1 || n_ref > kMaxRef) return fail(STEIN_ICP_E_INVALID, "need nq >= 0 and 1 <= n_ref < 2^31 - 64");
+    if (nq > ((int64_t)1 << 31) / n_ref) return fail(STEIN_ICP_E_INVALID, "nq * n_ref must be at most 2^31");
+    if (!ref_xyz || (nq > 0 && (!q_xyz || !values))) return fail(STEIN_ICP_E_INVALID, "a pointer is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    PairDesc pd{};
+    pd.n_ref = n_ref;
+    pd.n_ref_pad = round_up(n_ref, kRefPad);
+    std::vector<float> h((size_t)n_ref * 3);
+    if (hipMemcpy(h.data(), ref_xyz, 12 * (size_t)n_ref, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(STEIN_ICP_E_DEVICE, "reading the reference cloud for its centroid failed");
+    bf16_centre(h.data(), n_ref, pd);
+    if (centre)
+        for (int i = 0; i < 4; ++i) centre[i] = pd.c0[i];
+    if (scale_exp) *scale_exp = pd.sexp;
+    if (nq == 0) return STEIN_ICP_OK;
+    const int64_t nq_pad = round_up(nq, 32);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = (size_t)round_up((int64_t)(off + bytes), 256);
+        return o;
+    };
+    const size_t o_q = take(16 * (size_t)nq_pad), o_r = take(16 * (size_t)pd.n_ref_pad);
+    const size_t o_ap = take(64 * (size_t)pd.n_ref_pad), o_d = take(sizeof(PairDesc)), o_f = take(64);
+    char* mem = nullptr;
+    if (hipMalloc(&mem, off) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(STEIN_ICP_E_NOMEM, "device allocation failed");
+    }
+    int flag = 0, rc = STEIN_ICP_OK;
+    float4* q4 = (float4*)(mem + o_q);
+    float4* r4 = (float4*)(mem + o_r);
+    PairDesc* d_pd = (PairDesc*)(mem + o_d);
+    int* fl = (int*)(mem + o_f);
+    hipError_t e = hipMemsetAsync(fl, 0, 64, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_pd, &pd, sizeof(pd), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(pack_points_kernel, grid1d(nq_pad, 256), dim3(256), 0, s, q_xyz, nq, nq_pad, q4, fl);
+        hipLaunchKernelGGL(pack_points_kernel, grid1d(pd.n_ref_pad, 256), dim3(256), 0, s, ref_xyz, n_ref,
+                           pd.n_ref_pad, r4, fl);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, fl, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && flag) rc = fail(STEIN_ICP_E_INVALID, "a coordinate is non-finite or above 1e9");
+    if (e == hipSuccess && !rc) {
+        e = launch_pack_bf16(d_pd, 1, pd.n_ref_pad / kRefPad, r4, (uint4*)(mem + o_ap), screen_fmt(mode), s);
+        if (e == hipSuccess)
+            e = launch_screen_values(d_pd, pd.n_ref_pad, (const uint4*)(mem + o_ap), q4, nq, screen_fmt(mode), values, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    if (e != hipSuccess) rc = fail(STEIN_ICP_E_DEVICE, std::string("stein_icp_screen_values: ") + hipGetErrorString(e));
+    (void)hipFree(mem);
+    return rc;
+}
+
 namespace {
 
 // Scratch of stein_icp_nn_noalloc: device memory of this library's code

@@ -9,6 +9,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libstein_icp.so")
 
@@ -64,7 +66,8 @@ EXPORTS = [
     "stein_icp_get_diagnostics", "stein_icp_shape", "stein_icp_nn_tiling", "stein_icp_set_nn_tiling",
     "stein_icp_stage_times", "stein_icp_time_nn", "stein_icp_nn_rescans",
     "stein_icp_destroy",
-    "stein_icp_last_error", "stein_icp_nn", "stein_icp_nn_noalloc", "stein_icp_make_schedule",
+    "stein_icp_last_error", "stein_icp_nn", "stein_icp_nn_noalloc", "stein_icp_screen_values",
+    "stein_icp_make_schedule",
     "stein_icp_make_init",
     "stein_icp_knn", "stein_icp_normals", "stein_icp_get_normals", "stein_icp_posterior_scores",
 ]
@@ -108,6 +111,7 @@ def lib():
     L.stein_icp_last_error.restype = C.c_char_p
     L.stein_icp_nn.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
     L.stein_icp_nn_noalloc.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
+    L.stein_icp_screen_values.argtypes = [vp, i64, vp, i64, i32, vp, vp, C.POINTER(i32), vp]
     L.stein_icp_knn.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
     L.stein_icp_normals.argtypes = [vp, i64, i32, vp, vp, vp]
     L.stein_icp_get_normals.argtypes = [vp, vp, vp]
@@ -364,6 +368,20 @@ def stein_icp_nn_noalloc(q, ref, mode=NN_FP32, idx=None, d2=None, stream=None):
     _check("stein_icp_nn_noalloc", lib().stein_icp_nn_noalloc(_ptr(q), q.shape[0], _ptr(ref), ref.shape[0],
                                                               int(mode), _ptr(idx), _ptr(d2), _stream(stream)))
     return idx, d2
+
+
+def stein_icp_screen_values(q, ref, mode=NN_F16_RERANK, stream=None):
+    """(values (nq, M) float32 on the device, centre (4,) and scale exponent)
+    of a matrix-core screen's raw screened distances."""
+    import torch
+    _need(q, torch.float32, (q.shape[0], 3), "q")
+    _need(ref, torch.float32, (ref.shape[0], 3), "ref")
+    vals = torch.empty((q.shape[0], ref.shape[0]), dtype=torch.float32, device=q.device)
+    centre = (C.c_float * 4)()
+    e = C.c_int32()
+    _check("stein_icp_screen_values", lib().stein_icp_screen_values(
+        _ptr(q), q.shape[0], _ptr(ref), ref.shape[0], int(mode), _ptr(vals), centre, C.byref(e), _stream(stream)))
+    return vals, np.array(centre[:], dtype=np.float32), e.value
 
 
 def stein_icp_knn(q, ref, k, stream=None):
