@@ -178,8 +178,8 @@ PINNED_TILING = {
     ("kinect", "bf16"): "2,8,20096,0",
     ("kinect", "f16"): "2,8,20096,0",
     ("lidar", "fp32"): "4,8,4096,0",
-    ("lidar", "bf16"): "2,8,50176,0",
-    ("lidar", "f16"): "2,8,100000,0",
+    ("lidar", "bf16"): "2,4,50176,0",
+    ("lidar", "f16"): "2,4,50016,0",
 }
 
 

@@ -37,10 +37,13 @@
 // sum is bounded as if each of its additions lost up to one FP32 ulp of its
 // partial sum (truncation as well as rounding to nearest), 2u of the
 // magnitudes per addition, which measured errors on stress inputs stay well
-// inside. Each lane also keeps s2, the smallest block minimum of its
-// rows outside its best block. After the workgroup merges its keys into the
-// chunk minimum F_wg, a lane whose references outside its best block all
-// satisfy F > F_wg -- guaranteed when s2 - 60 u (|q_c| + R')^2 > F_wg (1 + 8 u)
+// inside. Each lane keeps, per block of its rows, a key: the block minimum
+// with its low significand bits replaced by the block's offset, and the
+// smallest two keys; the smallest names the best block, the second bounds
+// every other block's minimum from below to within 2^kb ulps (s2). After
+// the workgroup merges its keys into the chunk minimum F_wg, a lane whose
+// references outside its best block all satisfy F > F_wg -- guaranteed when
+// s2 - 60 u (|q_c| + R')^2 > F_wg (1 + 8 u)
 // with R' = min(R, |q_c| + sqrt(F_wg)), as only references within sqrt(F_wg)
 // of the query can win -- has lost nothing; otherwise that lane's own rows
 // of its wavefront's blocks are searched again in FP32 by the wavefront and
@@ -407,13 +410,21 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     const uint4* __restrict__ ap0 = a.apack + pd.apack_off + (c0 / kBlk) * kStride + lane;
     const uint4* __restrict__ ap1 = a.apack + pd.apack_off + (c0 / kBlk) * kStride + kWave + j;
 
-    float best[G], sec[G];   // best block minimum, and the smallest of the other blocks
-    int32_t bblk[G];
+    // Block keys: a block minimum's FP32 bits with the low kb bits replaced
+    // by the block's offset in the wavefront's range. A key is a finite
+    // float within 2^kb ulps of the minimum it stands for, so float
+    // comparisons order blocks by their minima (to that resolution) and the
+    // best key names its block: no compare-and-select per block.
+    const int kb = uniform(t1 - t0 > 1 ? 32 - __builtin_clz((uint32_t)(t1 - t0 - 1)) : 0);
+    const uint32_t kmask = ~((1u << kb) - 1u);
+    // the mask held in a vector register: a three-operand instruction reads
+    // at most one scalar, the block offset, so the key takes one and-or
+    const uint32_t vmask = (uint32_t)__builtin_amdgcn_mov_dpp((int)kmask, 0xE4, 0xF, 0xF, false);
+    float best[G], sec[G];   // smallest block key, and the smallest of the other blocks' keys
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         best[g] = __builtin_inff();
         sec[g] = __builtin_inff();
-        bblk[g] = t0;
     }
     const auto products = [&](const uint4& f0, const uint4& f1, f32x16_t (&acc)[G]) {
         if constexpr (F16) {
@@ -437,19 +448,19 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
             for (int g = 0; g < G; ++g) acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1[g], acc[g], 0, 0, 0);
         }
     };
-    // minimum of the lane's sixteen values of block blk; the new second
-    // smallest block minimum is the median of (best, sec, mn) as best <= sec
+    // key of the minimum of the lane's sixteen values of block blk; the new
+    // second smallest key is the median of (best, sec, key) as best <= sec
     const auto take_min = [&](const f32x16_t (&acc)[G], int32_t blk) {
+        const uint32_t off = (uint32_t)(blk - t0);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             float mn = __builtin_fminf(__builtin_fminf(acc[g][0], acc[g][1]), acc[g][2]);
 #pragma unroll
             for (int t = 3; t < 15; t += 2) mn = __builtin_fminf(__builtin_fminf(mn, acc[g][t]), acc[g][t + 1]);
             mn = __builtin_fminf(mn, acc[g][15]);
-            sec[g] = __builtin_amdgcn_fmed3f(best[g], sec[g], mn);
-            const bool better = mn < best[g];
-            best[g] = better ? mn : best[g];
-            bblk[g] = better ? blk : bblk[g];
+            const float key = __uint_as_float((__float_as_uint(mn) & vmask) | off);
+            sec[g] = __builtin_amdgcn_fmed3f(best[g], sec[g], key);
+            best[g] = __builtin_fminf(best[g], key);
         }
     };
     // fragments of block blk, clamped into the range (loads past its end
@@ -533,7 +544,8 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     for (int g = 0; g < G; ++g) {
         const int64_t qi = qbase + 32 * g + j;
         const float4 qf = qi < nq ? a.queries[pd.q_off + qi] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const int64_t rb = (int64_t)bblk[g] * kBlk;
+        const int32_t bblk = min(t0 + (int32_t)(__float_as_uint(best[g]) & ~kmask), t1 - 1);
+        const int64_t rb = (int64_t)bblk * kBlk;
         uint64_t k = ~0ull;
         if (t0 < t1) {
 #pragma unroll 4
@@ -591,6 +603,12 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
                 // distance): that norm, when below R, bounds the error
                 const double rmax = fmin((double)pd.c0[3], qn + sqrt((double)fwg));
                 const double span = (qn + rmax) * (1.0 + 0x1.0p-20);
+                // the other blocks' minima are at least the second key less
+                // its 2^kb ulps (infinite with no other block; no bound when
+                // the offsets would take most of the significand: every lane
+                // is searched again)
+                const double sd = (double)sec[g];
+                const double s2 = kb > 20 ? -HUGE_VAL : isinf(sd) ? sd : sd - ldexp(fabs(sd), kb - 22);
                 if constexpr (F16) {
                     // in scaled units: S and the bound carry 4^sexp, the
                     // absolute term of the bound is added there
@@ -598,10 +616,10 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
                     const double sp = span * s1;
                     const double margin = 56.0 * u * sp * sp + 0x1.0p-22 * (sp + 1.0);
                     fail = ((far_q >> g) & 1u) != 0u ||
-                           !((double)sec[g] - margin > (double)fwg * (s1 * s1) * (1.0 + 8.0 * u));
+                           !(s2 - margin > (double)fwg * (s1 * s1) * (1.0 + 8.0 * u));
                 } else {
                     const double margin = 60.0 * u * span * span;
-                    fail = !((double)sec[g] - margin > (double)fwg * (1.0 + 8.0 * u));
+                    fail = !(s2 - margin > (double)fwg * (1.0 + 8.0 * u));
                 }
             }
             unsigned long long mask = __ballot(fail);
@@ -693,8 +711,11 @@ __global__ __launch_bounds__(kWave) void screen_values_kernel(const PairDesc* __
     }
 }
 
+// Two queries per lane: at least two wavefronts per SIMD (at most 256
+// registers), so workgroups of four wavefronts run two to a compute unit;
+// one query per lane: four per SIMD.
 template <int Q, int W, int FMT>
-__global__ __launch_bounds__(kWave * W, (Q == 1 && W == 8) ? 4 : 1) void nn_bf16_kernel(NNBf16Args a)
+__global__ __launch_bounds__(kWave * W, Q == 1 ? 4 : 2) void nn_bf16_kernel(NNBf16Args a)
 {
     __shared__ uint64_t sk[W][kWave * Q];
     for (int64_t it = blockIdx.x; it < a.nwork; it += gridDim.x) nn_bf16_item<Q, W, FMT>(a, a.work[it], sk);

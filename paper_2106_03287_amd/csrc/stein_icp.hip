@@ -626,7 +626,7 @@ int autotune(stein_icp_ctx* c, hipStream_t s)
     const bool bf16 = is_screen(c->cfg.nn_mode);
     for (int q : {1, 2, 4})
         for (int w : {4, 8, 16})
-            for (int64_t pw : {64, 128, 256, 512, 1024, 2048, 4096}) {
+            for (int64_t pw : {64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384}) {
                 if (bf16 && !nn_bf16_shape_ok(q, w)) continue;
                 Tiling t;
                 t.q = q;
