@@ -194,8 +194,8 @@ def main():
     ap.add_argument("--workers", type=int, default=16,
                     help="host processes generating the proposal workload's pairs (1: in process)")
     ap.add_argument("--nn", default="auto", choices=["auto", "fp32", "bf16", "f16"],
-                    help="nearest-neighbour search: FP32, or the certified BF16 matrix-core screen (the same "
-                         "answers); auto takes the faster for the workload")
+                    help="nearest-neighbour search: FP32, or a certified matrix-core screen, BF16 x 3 or FP16 x 2 "
+                         "(the same answers); auto takes the faster for the workload")
     ap.add_argument("--metric", default="point", choices=["point", "plane"],
                     help="ICP error metric: point-to-point (Eqs. 4-5) or point-to-plane (normals at init)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -462,7 +462,7 @@ def run_mc(args):
     prob = synth.make_problem("kinect", 0)
     T = args.iters or prob.T
     R = args.runs
-    nn = "bf16" if args.nn == "auto" else args.nn
+    nn = "f16" if args.nn == "auto" else args.nn
     nn_mode = NN_MODE[nn]
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     src, ref = dev(prob.pair.src), dev(prob.pair.ref)
@@ -618,7 +618,7 @@ PROPOSAL_MACS_PER_PAIR = 2 * 4096 * (3 * 64 + 64 * 128 + 128 * 256) + 512 * 256 
 def run_proposal(args):
     """Time to MMD <= 0.05 on held-out pairs of the proposal's test split
     (cuboid and Kinect-shaped, alternating): the committed network plus
-    Stein ICP with the certified BF16 search, against plain Stein ICP with
+    Stein ICP with the certified FP16 x 2 search, against plain Stein ICP with
     the FP32 search from the uniform draw; MMD against the plain posterior
     (300 iterations from another draw), dimensions standardised by its
     spread, unbiased per pair, aggregated as sqrt(mean)."""
@@ -648,7 +648,7 @@ def run_proposal(args):
     achieved = n * PROPOSAL_MACS_PER_PAIR * 2 / (net_ms * 1e-3) / 1e12
     reached = res["n_star"]["proposal"] is not None
     out = {
-        "metric": "time-to-MMD<=0.05 vs plain (proposal + BF16 search)",
+        "metric": "time-to-MMD<=0.05 vs plain (proposal + FP16 x 2 search)",
         "value": round(res["proposal_ms"], 3) if reached else None,
         "unit": "ms",
         "n_gpus": 1,
@@ -658,10 +658,10 @@ def run_proposal(args):
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16 network, bf16+f32 search and f64 Stein ICP (proposal); f32 search (plain)",
+        "dtype": "bf16 network, f16+f32 search and f64 Stein ICP (proposal); f32 search (plain)",
         "data": "synthetic",
         "config": {"workload": "proposal", "pairs": n, "K": 100, "T_reference": T, "threshold": res["threshold"],
-                   "nn_proposal": "bf16", "nn_plain": "fp32",
+                   "nn_proposal": "f16", "nn_plain": "fp32",
                    "step": "network inputs, network and n* Stein iterations on every pair (proposal); "
                            "n* iterations from the uniform draw (plain)"},
         "n_star_proposal": res["n_star"]["proposal"],
