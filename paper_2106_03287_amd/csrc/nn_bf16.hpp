@@ -474,7 +474,61 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
         if constexpr (F16) f1 = f0;   // unused
         else f1 = ap1[(int64_t)b * kStride];
     };
-    if constexpr (G >= 4) {
+    if constexpr (G >= 4 && F16) {
+        // The pipeline below with four fragment buffers (FP16 x 2 fragments
+        // take one uint4, so the buffers fit in 256 registers): each refill
+        // takes the block four ahead, four blocks of load latency.
+        if (t0 < t1) {
+            uint4 fa0, fa1, fb0, fb1, fc0, fc1, fd0, fd1;
+            f32x16_t accp[G], accc[G];
+            frag(t0, fa0, fa1);
+            frag(t0 + 1, fb0, fb1);
+            frag(t0 + 2, fc0, fc1);
+            frag(t0 + 3, fd0, fd1);
+            products(fa0, fa1, accp);   // block t0
+            frag(t0 + 4, fa0, fa1);
+            int32_t b = t0 + 1;
+            // fb, fc, fd, fa hold blocks b .. b + 3 at the top of every trip
+            for (; b + 3 < t1; b += 4) {
+                products(fb0, fb1, accc);   // block b
+                frag(b + 4, fb0, fb1);
+                take_min(accp, b - 1);
+                __builtin_amdgcn_sched_barrier(0);
+                products(fc0, fc1, accp);   // block b + 1
+                frag(b + 5, fc0, fc1);
+                take_min(accc, b);
+                __builtin_amdgcn_sched_barrier(0);
+                products(fd0, fd1, accc);   // block b + 2
+                frag(b + 6, fd0, fd1);
+                take_min(accp, b + 1);
+                __builtin_amdgcn_sched_barrier(0);
+                products(fa0, fa1, accp);   // block b + 3
+                frag(b + 7, fa0, fa1);
+                take_min(accc, b + 2);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // zero to three blocks remain; accp holds block b - 1
+            if (b < t1) {
+                products(fb0, fb1, accc);
+                take_min(accp, b - 1);
+                if (b + 1 < t1) {
+                    products(fc0, fc1, accp);
+                    take_min(accc, b);
+                    if (b + 2 < t1) {
+                        products(fd0, fd1, accc);
+                        take_min(accp, b + 1);
+                        take_min(accc, b + 2);
+                    } else {
+                        take_min(accp, b + 1);
+                    }
+                } else {
+                    take_min(accc, b);
+                }
+            } else {
+                take_min(accp, b - 1);
+            }
+        }
+    } else if constexpr (G >= 4) {
         // Software pipeline: the products of block b are issued before the
         // minimum of block b - 1 is taken, so the matrix pipeline and the
         // vector ALU work on different blocks (two accumulator sets); two

@@ -523,8 +523,9 @@ def _grid_problem():
 def test_bf16_screen_every_block_count_per_wavefront(q, w, mode):
     """Chunks of 1 to 89 blocks of 32 references give the wavefronts of a
     workgroup 0 to 22 blocks each: every trip count of the screen's block
-    loops (the two-buffer loop and the software pipeline, both tails) and
-    ragged last chunks. The first iteration's matches equal the oracle's
+    loops (the two-buffer loop, and the software pipeline with two fragment
+    buffers (BF16 x 3) or four (FP16 x 2), with all their tails) and ragged
+    last chunks. The first iteration's matches equal the oracle's
     (lowest index on ties), on the cuboid pair and on an all-ties grid."""
     prob = synth.make_problem("cuboid", 0, T=1)
     cases = [(prob.pair.src, prob.pair.ref, prob.theta0, prob.schedule, prob.K, prob.m, prob.schedule.shape[0]),
