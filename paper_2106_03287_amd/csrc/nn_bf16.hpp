@@ -353,7 +353,8 @@ __global__ __launch_bounds__(kCentreThreads) void bf16_centre_kernel(PairDesc* _
 // A work item holds 64 Q queries (as in the FP32 search), taken as 2 Q groups
 // of 32 by every wavefront of the workgroup.
 template <int Q, int W, int FMT>
-__device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem w, uint64_t (*sk)[kWave * Q])
+__device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem w, uint64_t (*sk)[kWave * Q],
+                                             float (*sm)[kWave * Q])
 {
     constexpr bool F16 = FMT == kFmtF16x2;
     constexpr int G = 2 * Q;   // query groups of 32
@@ -589,6 +590,87 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
         }
     }
 
+    constexpr double u = 0x1.0p-24;
+    // The screen's error margin for a query of centred norm qn whose chunk
+    // minimum is fw (an FP32 squared distance), in the screen's units. A
+    // reference that could match or beat fw lies within sqrt(fw) of the
+    // query, so its centred norm is at most qn + sqrt(fw) (triangle
+    // inequality; the 2^-20 slack covers the rounding of the centring and
+    // of the FP32 distance): that norm, when below R, bounds the error.
+    const auto margin_of = [&](double qn, double fw) {
+        const double rmax = fmin((double)pd.c0[3], qn + sqrt(fw));
+        const double span = (qn + rmax) * (1.0 + 0x1.0p-20);
+        if constexpr (F16) {
+            // in scaled units: S and the bound carry 4^sexp, the absolute
+            // term of the bound is added there
+            const double sp = ldexp(span, pd.sexp);
+            return 56.0 * u * sp * sp + 0x1.0p-22 * (sp + 1.0);
+        } else {
+            return 60.0 * u * span * span;
+        }
+    };
+    const double unit2 = F16 ? ldexp(1.0, 2 * pd.sexp) : 1.0;   // screen units per squared input unit
+    // every block minimum a key stands for is at least the key less its
+    // 2^kb ulps (no bound when the offsets would take most of the
+    // significand: every lane is then searched again)
+    const auto lower = [&](float key) {
+        const double d = key;
+        return kb > 20 ? -HUGE_VAL : isinf(d) ? d : d - ldexp(fabs(d), kb - 22);
+    };
+    // (the queries are loaded again rather than kept from the prologue: the
+    // pointer is passed through an empty asm statement so that the compiler
+    // does not carry them through the block loop in registers)
+    const float4* qsrc = a.queries + pd.q_off;
+    asm volatile("" : "+v"(qsrc));
+    float4 qv[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t qi = qbase + 32 * g + j;
+        qv[g] = qi < nq ? qsrc[qi] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    // centred norm of a query (recomputed where needed: registers are short)
+    const auto qnorm = [&](const float4& q) {
+        float c[3];
+        {
+#pragma clang fp contract(off)
+            c[0] = q.x - pd.c0[0];
+            c[1] = q.y - pd.c0[1];
+            c[2] = q.z - pd.c0[2];
+        }
+        return sqrt((double)c[0] * c[0] + (double)c[1] * c[1] + (double)c[2] * c[2]);
+    };
+
+    // The smallest key of each query over the workgroup's lanes. Only a lane
+    // whose best block could hold the query's chunk minimum reranks it: one
+    // whose key, less the margin, is within the margin of that smallest key
+    // (the lane holding it always does). The others certify all of their
+    // blocks, the best included, from their best key below.
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const float m = fminf(best[g], __shfl_xor(best[g], 32));
+        if (h == 0) sm[wave][32 * g + j] = m;
+    }
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < kWave * Q; jj += kWave * W) {
+        float m0 = sm[0][jj];
+#pragma unroll
+        for (int v = 1; v < W; ++v) m0 = fminf(m0, sm[v][jj]);
+        sm[0][jj] = m0;
+    }
+    __syncthreads();
+    uint32_t rerank = 0u;   // groups whose best block this lane reranks
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const float m = sm[0][32 * g + j];
+        const int64_t qi = qbase + 32 * g + j;
+        const bool far = F16 && ((far_q >> g) & 1u) != 0u;   // searched again in FP32 below
+        if (qi < nq && t0 < t1 && !far) {
+            const double hi = (double)m + ldexp(fabs((double)m), kb - 22);   // the smallest block minimum, from above
+            const double marg = margin_of(qnorm(qv[g]), fmax(hi, 0.0) / unit2 * (1.0 + 0x1.0p-10));
+            if (!(lower(best[g]) - marg > (hi + marg) * (1.0 + 8.0 * u))) rerank |= 1u << g;
+        }
+    }
+
     // exact FP32 rerank of the lane's sixteen references in its best block
     // (keyed by the reference index), then the minimum over the two
     // lanes of each query
@@ -596,12 +678,11 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     uint64_t key[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int64_t qi = qbase + 32 * g + j;
-        const float4 qf = qi < nq ? a.queries[pd.q_off + qi] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 qf = qv[g];
         const int32_t bblk = min(t0 + (int32_t)(__float_as_uint(best[g]) & ~kmask), t1 - 1);
         const int64_t rb = (int64_t)bblk * kBlk;
         uint64_t k = ~0ull;
-        if (t0 < t1) {
+        if ((rerank >> g) & 1u) {
 #pragma unroll 4
             for (int t = 0; t < 16; ++t) {
                 const int row = blk_row(t, h);
@@ -630,7 +711,6 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     // has its own rows of its own blocks (16 (t1 - t0) references) searched
     // again in FP32 by its wavefront, folded into the chunk minimum in LDS
     if (t0 < t1) {
-        constexpr double u = 0x1.0p-24;
         const int64_t nref = 16 * (t1 - t0);
         // gathers kept in flight together (one query per lane: the
         // unrolled loop's registers would cost occupancy)
@@ -641,40 +721,12 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
             bool fail = false;
             if (qi < nq) {
                 const float fwg = __uint_as_float((uint32_t)(sk[0][32 * g + j] >> 32));
-                const float4 qf = a.queries[pd.q_off + qi];
-                float c[3];
-                {
-#pragma clang fp contract(off)
-                    c[0] = qf.x - pd.c0[0];
-                    c[1] = qf.y - pd.c0[1];
-                    c[2] = qf.z - pd.c0[2];
-                }
-                const double qn = sqrt((double)c[0] * c[0] + (double)c[1] * c[1] + (double)c[2] * c[2]);
-                // a reference that could match or beat fwg lies within
-                // sqrt(fwg) of the query, so its centred norm is at most
-                // qn + sqrt(fwg) (triangle inequality; the 2^-20 slack
-                // covers the rounding of the centring and of the FP32
-                // distance): that norm, when below R, bounds the error
-                const double rmax = fmin((double)pd.c0[3], qn + sqrt((double)fwg));
-                const double span = (qn + rmax) * (1.0 + 0x1.0p-20);
-                // the other blocks' minima are at least the second key less
-                // its 2^kb ulps (infinite with no other block; no bound when
-                // the offsets would take most of the significand: every lane
-                // is searched again)
-                const double sd = (double)sec[g];
-                const double s2 = kb > 20 ? -HUGE_VAL : isinf(sd) ? sd : sd - ldexp(fabs(sd), kb - 22);
-                if constexpr (F16) {
-                    // in scaled units: S and the bound carry 4^sexp, the
-                    // absolute term of the bound is added there
-                    const double s1 = ldexp(1.0, pd.sexp);
-                    const double sp = span * s1;
-                    const double margin = 56.0 * u * sp * sp + 0x1.0p-22 * (sp + 1.0);
-                    fail = ((far_q >> g) & 1u) != 0u ||
-                           !(s2 - margin > (double)fwg * (s1 * s1) * (1.0 + 8.0 * u));
-                } else {
-                    const double margin = 60.0 * u * span * span;
-                    fail = !(s2 - margin > (double)fwg * (1.0 + 8.0 * u));
-                }
+                // a reranked lane's other blocks are bounded by its second
+                // key, a lane that did not rerank has all of them bounded by
+                // its best key
+                const double s2 = lower(((rerank >> g) & 1u) ? sec[g] : best[g]);
+                const bool far = F16 && ((far_q >> g) & 1u) != 0u;
+                fail = far || !(s2 - margin_of(qnorm(qv[g]), (double)fwg) > (double)fwg * unit2 * (1.0 + 8.0 * u));
             }
             unsigned long long mask = __ballot(fail);
             if (mask != 0ull && a.rescans != nullptr && lane == 0)
@@ -684,16 +736,16 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
                 mask &= mask - 1ull;
                 const int fj = b & 31, fh = b >> 5;
                 const float4 qf = a.queries[pd.q_off + qbase + 32 * g + fj];
-                uint64_t kb = ~0ull;
+                uint64_t kr = ~0ull;
 #pragma unroll kRescanUnroll
                 for (int64_t e = lane; e < nref; e += kWave) {
                     const int64_t r = c0 + (t0 + e / 16) * kBlk + blk_row((int)(e & 15), fh);
                     const float4 rr = a.ref4[pd.ref_off + r];
-                    kb = min(kb, pack_key(dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z), (uint32_t)r));
+                    kr = min(kr, pack_key(dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z), (uint32_t)r));
                 }
 #pragma unroll
-                for (int o = kWave / 2; o > 0; o >>= 1) kb = min(kb, (uint64_t)__shfl_xor((unsigned long long)kb, o));
-                if (lane == 0) atomicMin((unsigned long long*)&sk[0][32 * g + fj], (unsigned long long)kb);
+                for (int o = kWave / 2; o > 0; o >>= 1) kr = min(kr, (uint64_t)__shfl_xor((unsigned long long)kr, o));
+                if (lane == 0) atomicMin((unsigned long long*)&sk[0][32 * g + fj], (unsigned long long)kr);
             }
         }
     }
@@ -772,7 +824,8 @@ template <int Q, int W, int FMT>
 __global__ __launch_bounds__(kWave * W, Q == 1 ? 4 : 2) void nn_bf16_kernel(NNBf16Args a)
 {
     __shared__ uint64_t sk[W][kWave * Q];
-    for (int64_t it = blockIdx.x; it < a.nwork; it += gridDim.x) nn_bf16_item<Q, W, FMT>(a, a.work[it], sk);
+    __shared__ float sm[W][kWave * Q];
+    for (int64_t it = blockIdx.x; it < a.nwork; it += gridDim.x) nn_bf16_item<Q, W, FMT>(a, a.work[it], sk, sm);
 }
 
 }  // namespace sicp
