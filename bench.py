@@ -84,11 +84,22 @@ def gpu_info(host):
     return info
 
 
+def code_text(path):
+    """A source file's code with its comments and blank space taken out, so
+    that a fingerprint of it changes with the code and not with the comments
+    (the kernel sources hold no string literals)."""
+    import re
+    t = open(path).read()
+    t = re.sub(r"/\*.*?\*/", " ", t, flags=re.S)
+    t = re.sub(r"//[^\n]*", " ", t)
+    return " ".join(t.split())
+
+
 def nn_source_sha(nn="fp32"):
     import hashlib
     h = hashlib.sha256()
     for f in (NN_BF16_SOURCES if nn in SCREENS else NN_SOURCES):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+        h.update(code_text(os.path.join(ROOT, f)).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,5 +1,6 @@
-// Nearest neighbour (Eq. 1) with a BF16 matrix-core screen and an exact FP32
-// rerank.
+// Nearest neighbour (Eq. 1) with a matrix-core screen and an exact FP32
+// rerank, in two formats: BF16 x 3 (below) and FP16 x 2 (further down, the
+// faster; the same structure with one FP16 product per block).
 //
 // Screen: squared distances in the expanded form |q|^2 + |r|^2 - 2 q.r on
 // v_mfma_f32_32x32x16_bf16 with FP32 accumulation. Both sides are centred on
@@ -14,16 +15,19 @@
 // layout at init), the queries the B operand (32 per group, built once per
 // wavefront). Lane l owns query l % 32 of each group and receives rows
 // 8 i + 4 (l / 32) + 0..3 (i = 0..3) of each 32-reference block; it keeps
-// only the minimum of those sixteen values and the block where it fell. The
+// only a key of the minimum of those sixteen values per block (see the
+// certificate below). The
 // wide product gives each lane sixteen values to reduce per pair of matrix
 // instructions (three-input minimums), where a 16 x 16 product gives four
 // per instruction: the vector-ALU work per distance, which bounded a 16 x 16
 // screen, about halves.
 //
-// Rerank: each lane recomputes the exact FP32 distance (the same operation
-// sequence as the FP32 search) of its sixteen references in its best block,
-// keyed by the reference index; the two lanes of a query merge their
-// (distance, index) keys. The FP32 search keys by 16-reference tile instead;
+// Rerank: the workgroup first finds each query's smallest key over its
+// lanes; a lane whose best key, less the error margin, is within the margin
+// of it (the lane holding it always is) recomputes the exact FP32 distance
+// (the same operation sequence as the FP32 search) of its sixteen references
+// in its best block, keyed by the reference index; the two lanes of a query
+// merge their (distance, index) keys. The FP32 search keys by 16-reference tile instead;
 // both order by distance, then lowest index, so the chunk reduction is
 // shared, and an index key needs no tile resolution downstream.
 //
@@ -40,10 +44,11 @@
 // inside. Each lane keeps, per block of its rows, a key: the block minimum
 // with its low significand bits replaced by the block's offset, and the
 // smallest two keys; the smallest names the best block, the second bounds
-// every other block's minimum from below to within 2^kb ulps (s2). After
+// every other block's minimum from below to within 2^kb ulps (s2; for a
+// lane that did not rerank, the best key bounds all of its blocks). After
 // the workgroup merges its keys into the chunk minimum F_wg, a lane whose
-// references outside its best block all satisfy F > F_wg -- guaranteed when
-// s2 - 60 u (|q_c| + R')^2 > F_wg (1 + 8 u)
+// references outside its reranked block all satisfy F > F_wg -- guaranteed
+// when s2 - 60 u (|q_c| + R')^2 > F_wg (1 + 8 u)
 // with R' = min(R, |q_c| + sqrt(F_wg)), as only references within sqrt(F_wg)
 // of the query can win -- has lost nothing; otherwise that lane's own rows
 // of its wavefront's blocks are searched again in FP32 by the wavefront and
