@@ -631,7 +631,7 @@ def test_lidar_full_size_iteration_at_the_bench_shape(nn):
 
 
 def test_batched_uneven_pairs_bf16_equals_fp32_bitwise():
-    """Uneven pairs in one batch: the certified BF16 search gives the FP32
+    """Uneven pairs in one batch: both certified screens give the FP32
     search's particles bit for bit."""
     probs = synth.batched_problems(6, K=16, m=40, T=8, size_scale=0.3)
     out = {}
