@@ -30,9 +30,7 @@ __global__ __launch_bounds__(kSvgdThreads) void grad_bandwidth_kernel(GradArgs g
     extern __shared__ double lds[];
     const int64_t bw_blocks = 2 * (int64_t)bw_pairs;
     if ((int64_t)blockIdx.x < bw_blocks) {   // whole workgroup
-        SelectShared& sh = *reinterpret_cast<SelectShared*>(lds);
-        double* dyn = lds + (sizeof(SelectShared) + 15) / 16 * 2;
-        bandwidth_body(v, blockIdx.x >> 1, blockIdx.x & 1, sh, dyn);
+        bandwidth_role<kSvgdThreads>(v, blockIdx.x, lds);
         return;
     }
     const int64_t wg = (int64_t)blockIdx.x - bw_blocks;

@@ -11,27 +11,37 @@ bool nn_bf16_shape_ok(int q, int w)
     return (q == 1 && (w == 4 || w == 8 || w == 16)) || (q == 2 && (w == 4 || w == 8));
 }
 
-template <int FMT>
+// grid: the work items' workgroups; the bandwidth workgroups come on top
+template <int FMT, bool BW>
 static void launch_fmt(int q, int w, unsigned grid, const NNBf16Args& a, hipStream_t s)
 {
+    const dim3 g(grid + (BW ? (unsigned)a.bw_blocks : 0u));
+    const size_t lds = BW ? a.bw_lds : 0;
     if (q == 1) {
         switch (w) {
-        case 4: hipLaunchKernelGGL((nn_bf16_kernel<1, 4, FMT>), dim3(grid), dim3(kWave * 4), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((nn_bf16_kernel<1, 8, FMT>), dim3(grid), dim3(kWave * 8), 0, s, a); break;
-        default: hipLaunchKernelGGL((nn_bf16_kernel<1, 16, FMT>), dim3(grid), dim3(kWave * 16), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((nn_bf16_kernel<1, 4, FMT, BW>), g, dim3(kWave * 4), lds, s, a); break;
+        case 8: hipLaunchKernelGGL((nn_bf16_kernel<1, 8, FMT, BW>), g, dim3(kWave * 8), lds, s, a); break;
+        default: hipLaunchKernelGGL((nn_bf16_kernel<1, 16, FMT, BW>), g, dim3(kWave * 16), lds, s, a); break;
         }
     } else {
-        if (w == 4) hipLaunchKernelGGL((nn_bf16_kernel<2, 4, FMT>), dim3(grid), dim3(kWave * 4), 0, s, a);
-        else hipLaunchKernelGGL((nn_bf16_kernel<2, 8, FMT>), dim3(grid), dim3(kWave * 8), 0, s, a);
+        if (w == 4) hipLaunchKernelGGL((nn_bf16_kernel<2, 4, FMT, BW>), g, dim3(kWave * 4), lds, s, a);
+        else hipLaunchKernelGGL((nn_bf16_kernel<2, 8, FMT, BW>), g, dim3(kWave * 8), lds, s, a);
     }
 }
 
 hipError_t launch_nn_bf16_kernel(int q, int w, int fmt, unsigned grid, const NNBf16Args& a, hipStream_t s)
 {
     if (!nn_bf16_shape_ok(q, w)) return hipErrorInvalidValue;
-    if (fmt == kFmtF16x2) launch_fmt<kFmtF16x2>(q, w, grid, a, s);
-    else if (fmt == kFmtBf16x3) launch_fmt<kFmtBf16x3>(q, w, grid, a, s);
-    else return hipErrorInvalidValue;
+    const bool bw = a.bw_blocks > 0;
+    if (fmt == kFmtF16x2) {
+        if (bw) launch_fmt<kFmtF16x2, true>(q, w, grid, a, s);
+        else launch_fmt<kFmtF16x2, false>(q, w, grid, a, s);
+    } else if (fmt == kFmtBf16x3) {
+        if (bw) launch_fmt<kFmtBf16x3, true>(q, w, grid, a, s);
+        else launch_fmt<kFmtBf16x3, false>(q, w, grid, a, s);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -825,12 +825,20 @@ __global__ __launch_bounds__(kWave) void screen_values_kernel(const PairDesc* __
 // Two queries per lane: at least two wavefronts per SIMD (at most 256
 // registers), so workgroups of four wavefronts run two to a compute unit;
 // one query per lane: four per SIMD.
-template <int Q, int W, int FMT>
+// BW: the launch may carry bandwidth workgroups (a separate instantiation,
+// so launches without them run the search's code alone).
+template <int Q, int W, int FMT, bool BW>
 __global__ __launch_bounds__(kWave * W, Q == 1 ? 4 : 2) void nn_bf16_kernel(NNBf16Args a)
 {
     __shared__ uint64_t sk[W][kWave * Q];
     __shared__ float sm[W][kWave * Q];
-    for (int64_t it = blockIdx.x; it < a.nwork; it += gridDim.x) nn_bf16_item<Q, W, FMT>(a, a.work[it], sk, sm);
+    if (BW && (int)blockIdx.x < a.bw_blocks) {
+        extern __shared__ double bw_lds[];
+        bandwidth_role<kWave * W>(a.bw, blockIdx.x, bw_lds);
+        return;
+    }
+    for (int64_t it = blockIdx.x - a.bw_blocks; it < a.nwork; it += gridDim.x - a.bw_blocks)
+        nn_bf16_item<Q, W, FMT>(a, a.work[it], sk, sm);
 }
 
 }  // namespace sicp

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
+#include "svgd_select.hpp"
 
 namespace sicp {
 
@@ -23,6 +24,12 @@ struct NNBf16Args {
     uint64_t* partial;
     int64_t nwork;
     unsigned long long* rescans;   // if set: certificates that failed, accumulated
+    // bw_blocks > 0: the launch's first bw_blocks workgroups compute the
+    // iteration's median-heuristic bandwidths instead (bw_lds bytes of
+    // dynamic LDS each), beside the search
+    SvgdArgs bw;
+    int32_t bw_blocks;
+    uint32_t bw_lds;
 };
 
 // Shapes the screen is built for: q queries per lane (1 or 2) and w

@@ -212,6 +212,24 @@ bool const_bandwidth(const stein_icp_config& c)
     return c.bandwidth_mode == STEIN_ICP_BW_FIXED || c.num_particles < 2;
 }
 
+// With a matrix-core screen, dynamic LDS up to this (K up to about 128) and
+// at most two particles per compute unit (the gradient launch then holds
+// few workgroups, and the bandwidth selection beside them took longer than
+// the gradients), the median bandwidths run as extra workgroups of the
+// nearest-neighbour launch, beside the search. With many pairs the gradients
+// take longer than the selection, and the extra workgroups would only delay
+// the search. (The FP32 search keeps them in the gradient launch: the
+// selection's registers would cost it occupancy.)
+constexpr size_t kFusedBandwidthLds = 48 * 1024;
+int g_num_cus = 256;   // compute units of the device, read at the first init
+
+bool fused_bandwidth(const stein_icp_config& c, int64_t pairs)
+{
+    return is_screen(c.nn_mode) && !const_bandwidth(c) &&
+           bandwidth_role_lds_bytes(c.num_particles) <= kFusedBandwidthLds &&
+           pairs * c.num_particles <= 2 * (int64_t)g_num_cus;
+}
+
 SvgdParams svgd_params(const stein_icp_config& c)
 {
     SvgdParams p{};
@@ -285,7 +303,6 @@ constexpr int64_t kMaxRef = ((int64_t)1 << 31) - 64;
 
 dim3 grid1d(int64_t n, int threads) { return dim3((unsigned)ceil_div(std::max<int64_t>(n, 1), threads)); }
 
-int g_num_cus = 256;
 
 // Launch the NN kernel with q queries per lane and w wavefronts per workgroup.
 template <int Q>
@@ -474,6 +491,11 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
             b.queries = c->queries;
             b.partial = c->partial;
             b.rescans = c->rescans;
+            if (fused_bandwidth(c->cfg, c->P)) {
+                b.bw = svgd_args(c);
+                b.bw_blocks = 2 * c->P;
+                b.bw_lds = (uint32_t)bandwidth_role_lds_bytes(c->K);
+            }
             return launch_nn_bf16(c->tiling, (unsigned)c->work.size(), b, screen_fmt(c->cfg.nn_mode), s);
         }
         return launch_nn(c->tiling, (unsigned)c->work.size(), nn_args(c), s);
@@ -495,7 +517,7 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
     g.m = c->m;
     g.rows = c->rows;
     g.index_keys = is_screen(c->cfg.nn_mode) ? 1 : 0;
-    const int32_t bw_pairs = const_bandwidth(c->cfg) ? 0 : c->P;
+    const int32_t bw_pairs = const_bandwidth(c->cfg) || fused_bandwidth(c->cfg, c->P) ? 0 : c->P;
     const int64_t blocks = 2 * (int64_t)bw_pairs + ceil_div((int64_t)c->P * c->K, kGradGroups);
     hipLaunchKernelGGL(grad_bandwidth_kernel, dim3((unsigned)blocks), dim3(kSvgdThreads), grad_bw_lds_bytes(c->K), s,
                        g, svgd_args(c), c->P, bw_pairs);

@@ -366,6 +366,35 @@ def test_bandwidth_selection_degenerate_particle_sets(kind):
     _one_step_compare(prob)
 
 
+@pytest.mark.parametrize("kind", ["uniform", "identical", "two_clusters", "near_duplicates", "few_values"])
+def test_bandwidths_beside_the_screen_search_equal_the_gradient_launch(kind):
+    """With a screen and few particles in flight the median bandwidths run
+    as extra workgroups of the nearest-neighbour launch, on its workgroup
+    size (256, 512 or 1024 threads): h equals the gradient launch's (FP32
+    search, 1024 threads) bit for bit and the oracle's, and the iteration's
+    particles are the same, on degenerate particle sets too."""
+    prob = synth.make_problem("cuboid", 13, K=120, T=2)
+    if kind != "uniform":
+        prob.theta0 = _theta_variant(prob, kind, np.random.default_rng(5))
+    print(f"fused bandwidth case {kind}", flush=True)
+    _one_step_compare(prob)
+    sol = gpu_solver(prob)
+    sol.step(1)
+    want_h = sol.diagnostics()["h"].cpu().numpy()
+    want_th = sol.particles().cpu().numpy()
+    sol.close()
+    gcfg, _ = both_configs(prob)
+    for mode in (S.NN_F16_RERANK, S.NN_BF16_RERANK):
+        gcfg.nn_mode = mode
+        for q, w in ((2, 4), (2, 8), (1, 16)):
+            sol = S.SteinICP(gcfg, dev(prob.pair.src), dev(prob.pair.ref), dev(prob.theta0), dev(prob.schedule))
+            sol.set_tiling(q, w, 64 * w)
+            sol.step(1)
+            np.testing.assert_array_equal(sol.diagnostics()["h"].cpu().numpy(), want_h, err_msg=f"{mode} {q},{w}")
+            np.testing.assert_array_equal(sol.particles().cpu().numpy(), want_th, err_msg=f"{mode} {q},{w}")
+            sol.close()
+
+
 @pytest.mark.parametrize("K", [346, 347, 400])
 def test_bandwidth_keyed_and_global_paths(K):
     prob = synth.make_problem("cuboid", 14, K=K, m=8, T=2)
