@@ -817,7 +817,9 @@ __global__ __launch_bounds__(kWave) void screen_values_kernel(const PairDesc* __
         const int64_t r = blk * kBlk + blk_row(t, h);
         if (r < pd.n_ref) {
             const float x = F16 ? ldexpf(acc[t], -2 * pd.sexp) : acc[t];
-            values[qi * pd.n_ref + r] = far ? __builtin_nanf("") : x;
+            // the quiet NaN goes out as its bit pattern: this file is built
+            // with NaNs assumed away
+            reinterpret_cast<uint32_t*>(values)[qi * pd.n_ref + r] = far ? 0x7fc00000u : __float_as_uint(x);
         }
     }
 }
@@ -834,7 +836,7 @@ __global__ __launch_bounds__(kWave * W, Q == 1 ? 4 : 2) void nn_bf16_kernel(NNBf
     __shared__ float sm[W][kWave * Q];
     if (BW && (int)blockIdx.x < a.bw_blocks) {
         extern __shared__ double bw_lds[];
-        bandwidth_role<kWave * W>(a.bw, blockIdx.x, bw_lds);
+        bandwidth_role<kWave * W>(a.bw, blockIdx.x, a.bw_keyed != 0, bw_lds);
         return;
     }
     for (int64_t it = blockIdx.x - a.bw_blocks; it < a.nwork; it += gridDim.x - a.bw_blocks)

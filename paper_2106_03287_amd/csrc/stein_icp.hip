@@ -212,22 +212,32 @@ bool const_bandwidth(const stein_icp_config& c)
     return c.bandwidth_mode == STEIN_ICP_BW_FIXED || c.num_particles < 2;
 }
 
-// With a matrix-core screen, dynamic LDS up to this (K up to about 128) and
-// at most two particles per compute unit (the gradient launch then holds
-// few workgroups, and the bandwidth selection beside them took longer than
-// the gradients), the median bandwidths run as extra workgroups of the
-// nearest-neighbour launch, beside the search. With many pairs the gradients
-// take longer than the selection, and the extra workgroups would only delay
-// the search. (The FP32 search keeps them in the gradient launch: the
-// selection's registers would cost it occupancy.)
+// With a matrix-core screen, dynamic LDS up to this and at most two
+// particles per compute unit (the gradient launch then holds few
+// workgroups, and the bandwidth selection beside them took longer than the
+// gradients), the median bandwidths run as extra workgroups of the
+// nearest-neighbour launch, beside the search: with the pair keys in LDS up
+// to K of about 128, with the distances in global memory up to K of about
+// 490. With many pairs the gradients take longer than the selection, and the
+// extra workgroups would only delay the search. (The FP32 search keeps them
+// in the gradient launch: the selection's registers would cost it
+// occupancy.) Every workgroup of the launch takes the dynamic LDS, so the
+// bound keeps two search workgroups per compute unit.
 constexpr size_t kFusedBandwidthLds = 48 * 1024;
 int g_num_cus = 256;   // compute units of the device, read at the first init
 
+// Whether the fused bandwidth workgroups keep the pair keys in LDS.
+bool fused_bandwidth_keyed(int K)
+{
+    return bandwidth_keyable(K) && bandwidth_role_lds_bytes(K, true) <= kFusedBandwidthLds;
+}
+
 bool fused_bandwidth(const stein_icp_config& c, int64_t pairs)
 {
+    const int K = c.num_particles;
     return is_screen(c.nn_mode) && !const_bandwidth(c) &&
-           bandwidth_role_lds_bytes(c.num_particles) <= kFusedBandwidthLds &&
-           pairs * c.num_particles <= 2 * (int64_t)g_num_cus;
+           bandwidth_role_lds_bytes(K, fused_bandwidth_keyed(K)) <= kFusedBandwidthLds &&
+           pairs * K <= 2 * (int64_t)g_num_cus;
 }
 
 SvgdParams svgd_params(const stein_icp_config& c)
@@ -494,7 +504,8 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
             if (fused_bandwidth(c->cfg, c->P)) {
                 b.bw = svgd_args(c);
                 b.bw_blocks = 2 * c->P;
-                b.bw_lds = (uint32_t)bandwidth_role_lds_bytes(c->K);
+                b.bw_keyed = fused_bandwidth_keyed(c->K) ? 1 : 0;
+                b.bw_lds = (uint32_t)bandwidth_role_lds_bytes(c->K, b.bw_keyed != 0);
             }
             return launch_nn_bf16(c->tiling, (unsigned)c->work.size(), b, screen_fmt(c->cfg.nn_mode), s);
         }

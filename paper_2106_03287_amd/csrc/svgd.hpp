@@ -1,19 +1,22 @@
 // Stein direction (Eq. 16) and particle update (Eq. 12 with Adam).
 //
 // Per iteration:
-//  * bandwidth_body, one 1024-thread workgroup per (pair, block), run by
-//    the workgroups of the gradient launch that carry no particles:
-//    block 0 the translation kernel, block 1 the wrapped-angle rotation
-//    kernel of Eq. 17. The median heuristic h = med^2 / ln K needs the middle
-//    order statistics of the K(K-1)/2 distances between distinct particles,
-//    found exactly: the distances are stored as 16-bit monotone keys in LDS
-//    (K up to about 345), a 4096-bin integer histogram of the keys' own range
-//    finds the bins of both middle ranks in one pass, and the exact FP64
-//    distances of those bins' few pairs are recomputed and ranked by counting
-//    (wider ranges narrow bin by bin).
-//    Larger K keep FP64 distances in global memory and bin by value. A radix
-//    select over IEEE-754 bit patterns covers the degenerate cases. It
-//    depends only on the particles, so it runs beside the gradients.
+//  * bandwidth_body, one workgroup per (pair, block): block 0 the
+//    translation kernel, block 1 the wrapped-angle rotation kernel of
+//    Eq. 17. It depends only on the particles, so it runs beside other
+//    work: as 1024-thread workgroups of the gradient launch that carry no
+//    particles, or (matrix-core screen, few particles in flight) as extra
+//    workgroups of the nearest-neighbour launch on its workgroup size.
+//    The median heuristic h = med^2 / ln K needs the middle order
+//    statistics of the K(K-1)/2 distances between distinct particles, found
+//    exactly: the distances are stored as 16-bit monotone keys in LDS (K up
+//    to about 345, where the launch's LDS allows), a 4096-bin integer
+//    histogram of the keys' own range finds the bins of both middle ranks in
+//    one pass, and the exact FP64 distances of those bins' few pairs are
+//    recomputed and ranked by counting (wider ranges narrow bin by bin).
+//    Otherwise the FP64 distances go to global memory and are binned by
+//    value. A radix select over IEEE-754 bit patterns covers the degenerate
+//    cases. Both forms return the same order statistics.
 //  * svgd_phi_update_kernel, one 256-thread workgroup per particle k:
 //    phi_k = (1/K) sum_l [G_l k(l,k) + grad_{theta_l} k(l,k)] with
 //    G_l = -N gbar_l + grad log p(theta_l) (Eq. 10 with Eqs. 14-15), threads

@@ -584,13 +584,19 @@ __device__ inline void select_pair_keyed(const uint16_t* key, int64_t n, int64_t
 // to this many pairs (K up to about 345); beyond, as FP64 in global memory.
 constexpr int64_t kMaxKeyedPairs = 60000;
 
+// Whether bandwidth_body may keep the pair keys of K particles in LDS.
+__host__ __device__ inline bool bandwidth_keyable(int K) { return (int64_t)K * (K - 1) / 2 <= kMaxKeyedPairs; }
+
 // grid (pairs, 2), 1024 threads. blockIdx.y: 0 translation, 1 rotation.
 // Dynamic LDS: K x 6 particles (FP64) followed by the 16-bit pair keys.
 // Median-heuristic bandwidth of pair p, block rot (0 translation, 1
-// rotation), by one 1024-thread workgroup; `sh` and `dyn`
-// (bandwidth_lds_bytes(K)) are the workgroup's LDS.
+// rotation), by one NT-thread workgroup; `sh` and `dyn`
+// (bandwidth_lds_bytes(K, keyed)) are the workgroup's LDS. `keyed` (only
+// where bandwidth_keyable(K)): the pair distances go to LDS as 16-bit keys,
+// else to global memory as FP64; both find the same exact order statistics.
 template <int NT>
-__device__ __forceinline__ void bandwidth_body(const SvgdArgs& a, int64_t p, int rot, SelectShared& sh, double* dyn)
+__device__ __forceinline__ void bandwidth_body(const SvgdArgs& a, int64_t p, int rot, bool keyed, SelectShared& sh,
+                                               double* dyn)
 {
     const int K = a.K;
     const int tid = threadIdx.x;
@@ -604,7 +610,7 @@ __device__ __forceinline__ void bandwidth_body(const SvgdArgs& a, int64_t p, int
     const int64_t np = (int64_t)K * (K - 1) / 2;
     const int64_t ra = (np - 1) / 2, rb = np / 2;
     double va, vb;
-    if (np <= kMaxKeyedPairs) {
+    if (keyed) {
         uint16_t* key = reinterpret_cast<uint16_t*>(dyn + 6 * K);
         // the keys, their range (per wavefront) and the cleared histogram
         // of the selection, under one barrier
@@ -641,26 +647,29 @@ __device__ __forceinline__ void bandwidth_body(const SvgdArgs& a, int64_t p, int
 }
 
 // LDS bytes of bandwidth_body besides SelectShared.
-inline size_t bandwidth_lds_bytes(int K)
+inline size_t bandwidth_lds_bytes(int K, bool keyed)
 {
     const int64_t np = (int64_t)K * (K - 1) / 2;
     size_t b = 48 * (size_t)K;
-    if (np <= kMaxKeyedPairs) b += 2 * (size_t)np;
+    if (keyed) b += 2 * (size_t)np;
     return (b + 15) / 16 * 16;
 }
 
 // Dynamic LDS bytes of a bandwidth workgroup (SelectShared, then the
 // particles and keys of bandwidth_body).
-inline size_t bandwidth_role_lds_bytes(int K) { return (sizeof(SelectShared) + 15) / 16 * 16 + bandwidth_lds_bytes(K); }
+inline size_t bandwidth_role_lds_bytes(int K, bool keyed)
+{
+    return (sizeof(SelectShared) + 15) / 16 * 16 + bandwidth_lds_bytes(K, keyed);
+}
 
 // Bandwidth workgroup b of a launch (pair b / 2, block b % 2) on NT threads;
-// lds: its dynamic LDS of bandwidth_role_lds_bytes(K) bytes.
+// lds: its dynamic LDS of bandwidth_role_lds_bytes(K, keyed) bytes.
 template <int NT>
-__device__ __forceinline__ void bandwidth_role(const SvgdArgs& v, int64_t b, double* lds)
+__device__ __forceinline__ void bandwidth_role(const SvgdArgs& v, int64_t b, bool keyed, double* lds)
 {
     SelectShared& sh = *reinterpret_cast<SelectShared*>(lds);
     double* dyn = lds + (sizeof(SelectShared) + 15) / 16 * 2;
-    bandwidth_body<NT>(v, b >> 1, (int)(b & 1), sh, dyn);
+    bandwidth_body<NT>(v, b >> 1, (int)(b & 1), keyed, sh, dyn);
 }
 
 }  // namespace sicp

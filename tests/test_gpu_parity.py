@@ -366,17 +366,20 @@ def test_bandwidth_selection_degenerate_particle_sets(kind):
     _one_step_compare(prob)
 
 
+@pytest.mark.parametrize("K", [120, 300])
 @pytest.mark.parametrize("kind", ["uniform", "identical", "two_clusters", "near_duplicates", "few_values"])
-def test_bandwidths_beside_the_screen_search_equal_the_gradient_launch(kind):
+def test_bandwidths_beside_the_screen_search_equal_the_gradient_launch(kind, K):
     """With a screen and few particles in flight the median bandwidths run
     as extra workgroups of the nearest-neighbour launch, on its workgroup
     size (256, 512 or 1024 threads): h equals the gradient launch's (FP32
     search, 1024 threads) bit for bit and the oracle's, and the iteration's
-    particles are the same, on degenerate particle sets too."""
-    prob = synth.make_problem("cuboid", 13, K=120, T=2)
+    particles are the same, on degenerate particle sets too. K = 120 keeps
+    the pair keys in LDS there; K = 300 (the LiDAR particle count) keeps the
+    distances in global memory there, while the gradient launch keys them."""
+    prob = synth.make_problem("cuboid", 13, K=K, T=2)
     if kind != "uniform":
         prob.theta0 = _theta_variant(prob, kind, np.random.default_rng(5))
-    print(f"fused bandwidth case {kind}", flush=True)
+    print(f"fused bandwidth case {kind} K={K}", flush=True)
     _one_step_compare(prob)
     sol = gpu_solver(prob)
     sol.step(1)
