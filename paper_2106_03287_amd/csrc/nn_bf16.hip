@@ -11,34 +11,43 @@ bool nn_bf16_shape_ok(int q, int w)
     return (q == 1 && (w == 4 || w == 8 || w == 16)) || (q == 2 && (w == 4 || w == 8));
 }
 
+int nn_bf16_key_span(int q, int w, int64_t min_chunk)
+{
+    return q == 2 && min_chunk / ((int64_t)kBlk * w) >= 192 ? 2 : 1;
+}
+
 // grid: the work items' workgroups; the bandwidth workgroups come on top
 template <int FMT, bool BW>
-static void launch_fmt(int q, int w, unsigned grid, const NNBf16Args& a, hipStream_t s)
+static void launch_fmt(int q, int w, int span, unsigned grid, const NNBf16Args& a, hipStream_t s)
 {
     const dim3 g(grid + (BW ? (unsigned)a.bw_blocks : 0u));
     const size_t lds = BW ? a.bw_lds : 0;
     if (q == 1) {
         switch (w) {
-        case 4: hipLaunchKernelGGL((nn_bf16_kernel<1, 4, FMT, BW>), g, dim3(kWave * 4), lds, s, a); break;
-        case 8: hipLaunchKernelGGL((nn_bf16_kernel<1, 8, FMT, BW>), g, dim3(kWave * 8), lds, s, a); break;
-        default: hipLaunchKernelGGL((nn_bf16_kernel<1, 16, FMT, BW>), g, dim3(kWave * 16), lds, s, a); break;
+        case 4: hipLaunchKernelGGL((nn_bf16_kernel<1, 4, FMT, BW, 1>), g, dim3(kWave * 4), lds, s, a); break;
+        case 8: hipLaunchKernelGGL((nn_bf16_kernel<1, 8, FMT, BW, 1>), g, dim3(kWave * 8), lds, s, a); break;
+        default: hipLaunchKernelGGL((nn_bf16_kernel<1, 16, FMT, BW, 1>), g, dim3(kWave * 16), lds, s, a); break;
         }
+    } else if (span == 2) {
+        if (w == 4) hipLaunchKernelGGL((nn_bf16_kernel<2, 4, FMT, BW, 2>), g, dim3(kWave * 4), lds, s, a);
+        else hipLaunchKernelGGL((nn_bf16_kernel<2, 8, FMT, BW, 2>), g, dim3(kWave * 8), lds, s, a);
     } else {
-        if (w == 4) hipLaunchKernelGGL((nn_bf16_kernel<2, 4, FMT, BW>), g, dim3(kWave * 4), lds, s, a);
-        else hipLaunchKernelGGL((nn_bf16_kernel<2, 8, FMT, BW>), g, dim3(kWave * 8), lds, s, a);
+        if (w == 4) hipLaunchKernelGGL((nn_bf16_kernel<2, 4, FMT, BW, 1>), g, dim3(kWave * 4), lds, s, a);
+        else hipLaunchKernelGGL((nn_bf16_kernel<2, 8, FMT, BW, 1>), g, dim3(kWave * 8), lds, s, a);
     }
 }
 
-hipError_t launch_nn_bf16_kernel(int q, int w, int fmt, unsigned grid, const NNBf16Args& a, hipStream_t s)
+hipError_t launch_nn_bf16_kernel(int q, int w, int fmt, int span, unsigned grid, const NNBf16Args& a,
+                                 hipStream_t s)
 {
-    if (!nn_bf16_shape_ok(q, w)) return hipErrorInvalidValue;
+    if (!nn_bf16_shape_ok(q, w) || (span != 1 && span != 2) || (span == 2 && q != 2)) return hipErrorInvalidValue;
     const bool bw = a.bw_blocks > 0;
     if (fmt == kFmtF16x2) {
-        if (bw) launch_fmt<kFmtF16x2, true>(q, w, grid, a, s);
-        else launch_fmt<kFmtF16x2, false>(q, w, grid, a, s);
+        if (bw) launch_fmt<kFmtF16x2, true>(q, w, span, grid, a, s);
+        else launch_fmt<kFmtF16x2, false>(q, w, span, grid, a, s);
     } else if (fmt == kFmtBf16x3) {
-        if (bw) launch_fmt<kFmtBf16x3, true>(q, w, grid, a, s);
-        else launch_fmt<kFmtBf16x3, false>(q, w, grid, a, s);
+        if (bw) launch_fmt<kFmtBf16x3, true>(q, w, span, grid, a, s);
+        else launch_fmt<kFmtBf16x3, false>(q, w, span, grid, a, s);
     } else {
         return hipErrorInvalidValue;
     }

@@ -15,8 +15,8 @@
 // layout at init), the queries the B operand (32 per group, built once per
 // wavefront). Lane l owns query l % 32 of each group and receives rows
 // 8 i + 4 (l / 32) + 0..3 (i = 0..3) of each 32-reference block; it keeps
-// only a key of the minimum of those sixteen values per block (see the
-// certificate below). The
+// only a key of the minimum of those sixteen values per block, or per two
+// blocks (see the certificate below). The
 // wide product gives each lane sixteen values to reduce per pair of matrix
 // instructions (three-input minimums), where a 16 x 16 product gives four
 // per instruction: the vector-ALU work per distance, which bounded a 16 x 16
@@ -25,8 +25,8 @@
 // Rerank: the workgroup first finds each query's smallest key over its
 // lanes; a lane whose best key, less the error margin, is within the margin
 // of it (the lane holding it always is) recomputes the exact FP32 distance
-// (the same operation sequence as the FP32 search) of its sixteen references
-// in its best block, keyed by the reference index; the two lanes of a query
+// (the same operation sequence as the FP32 search) of its rows of its best
+// key's blocks, keyed by the reference index; the two lanes of a query
 // merge their (distance, index) keys. The FP32 search keys by 16-reference tile instead;
 // both order by distance, then lowest index, so the chunk reduction is
 // shared, and an index key needs no tile resolution downstream.
@@ -41,13 +41,14 @@
 // sum is bounded as if each of its additions lost up to one FP32 ulp of its
 // partial sum (truncation as well as rounding to nearest), 2u of the
 // magnitudes per addition, which measured errors on stress inputs stay well
-// inside. Each lane keeps, per block of its rows, a key: the block minimum
-// with its low significand bits replaced by the block's offset, and the
-// smallest two keys; the smallest names the best block, the second bounds
-// every other block's minimum from below to within 2^kb ulps (s2; for a
-// lane that did not rerank, the best key bounds all of its blocks). After
-// the workgroup merges its keys into the chunk minimum F_wg, a lane whose
-// references outside its reranked block all satisfy F > F_wg -- guaranteed
+// inside. Each lane keeps, per one or two consecutive blocks of its rows, a
+// key: their minimum with its low significand bits replaced by the key's
+// offset, and the smallest two keys; the smallest names the best blocks, the
+// second bounds every other key's minimum from below to within 2^kb ulps
+// (s2; for a lane that did not rerank, the best key bounds all of its
+// blocks). After the workgroup merges its keys into the chunk minimum F_wg,
+// a lane whose references outside its reranked blocks all satisfy F > F_wg
+// -- guaranteed
 // when s2 - 60 u (|q_c| + R')^2 > F_wg (1 + 8 u)
 // with R' = min(R, |q_c| + sqrt(F_wg)), as only references within sqrt(F_wg)
 // of the query can win -- has lost nothing; otherwise that lane's own rows
@@ -228,6 +229,13 @@ constexpr int kBlk = kRefPad;   // references per block of the screen (the A ope
 // (lane / 32) of the 32 x 32 product.
 __device__ __forceinline__ int blk_row(int t, int h) { return 8 * (t >> 2) + 4 * h + (t & 3); }
 
+// Phases of a block in its key (see the block loop of nn_bf16_item).
+constexpr int kStart = 1, kEnd = 2, kBoth = 3;
+template <int P>
+struct PhaseT {
+    static constexpr int value = P;
+};
+
 // grid (blocks of 32 references / 4, groups) x 256 threads, one wavefront
 // per block: each lane's two A fragments (K slots 8 h .. 8 h + 7 and
 // 16 + 8 h .. +7 of row lane % 32). A block takes 128 uint4: the 64 lanes'
@@ -356,8 +364,8 @@ __global__ __launch_bounds__(kCentreThreads) void bf16_centre_kernel(PairDesc* _
 }
 
 // A work item holds 64 Q queries (as in the FP32 search), taken as 2 Q groups
-// of 32 by every wavefront of the workgroup.
-template <int Q, int W, int FMT>
+// of 32 by every wavefront of the workgroup. SPAN: blocks per key (1 or 2).
+template <int Q, int W, int FMT, int SPAN>
 __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem w, uint64_t (*sk)[kWave * Q],
                                              float (*sm)[kWave * Q])
 {
@@ -416,21 +424,28 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     const uint4* __restrict__ ap0 = a.apack + pd.apack_off + (c0 / kBlk) * kStride + lane;
     const uint4* __restrict__ ap1 = a.apack + pd.apack_off + (c0 / kBlk) * kStride + kWave + j;
 
-    // Block keys: a block minimum's FP32 bits with the low kb bits replaced
-    // by the block's offset in the wavefront's range. A key is a finite
-    // float within 2^kb ulps of the minimum it stands for, so float
-    // comparisons order blocks by their minima (to that resolution) and the
-    // best key names its block: no compare-and-select per block.
-    const int kb = uniform(t1 - t0 > 1 ? 32 - __builtin_clz((uint32_t)(t1 - t0 - 1)) : 0);
+    // Block keys: the minimum of kSB consecutive blocks (one or two), its
+    // FP32 bits with the low kb bits replaced by the key's offset in the
+    // wavefront's range. A key is a finite float within 2^kb ulps of the
+    // minimum it stands for, so float comparisons order keys by their minima
+    // (to that resolution) and the best key names its blocks: no
+    // compare-and-select per block. Two blocks per key save 1.5 vector
+    // instructions per block and group (one key update per two blocks) and
+    // double the rerank.
+    constexpr int kSB = SPAN;
+    const int32_t nkeys = (t1 - t0 + kSB - 1) / kSB;
+    const int kb = uniform(nkeys > 1 ? 32 - __builtin_clz((uint32_t)(nkeys - 1)) : 0);
     const uint32_t kmask = ~((1u << kb) - 1u);
     // the mask held in a vector register: a three-operand instruction reads
     // at most one scalar, the block offset, so the key takes one and-or
     const uint32_t vmask = (uint32_t)__builtin_amdgcn_mov_dpp((int)kmask, 0xE4, 0xF, 0xF, false);
     float best[G], sec[G];   // smallest block key, and the smallest of the other blocks' keys
+    float carry[G];          // minimum over the earlier blocks of the current key
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         best[g] = __builtin_inff();
         sec[g] = __builtin_inff();
+        carry[g] = __builtin_inff();
     }
     const auto products = [&](const uint4& f0, const uint4& f1, f32x16_t (&acc)[G]) {
         if constexpr (F16) {
@@ -454,21 +469,33 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
             for (int g = 0; g < G; ++g) acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1[g], acc[g], 0, 0, 0);
         }
     };
-    // key of the minimum of the lane's sixteen values of block blk; the new
-    // second smallest key is the median of (best, sec, key) as best <= sec
-    const auto take_min = [&](const f32x16_t (&acc)[G], int32_t blk) {
-        const uint32_t off = (uint32_t)(blk - t0);
+    // the minimum of the lane's sixteen values of block blk, and with the
+    // key's last block the key; the new second smallest key is the median of
+    // (best, sec, key) as best <= sec. phase: kStart a key's first block
+    // (its minimum kept in carry), kEnd its last, kBoth a key of one block
+    // (the loops below follow the parity of the block offset statically)
+    const auto take_min = [&](const f32x16_t (&acc)[G], int32_t blk, auto phase) {
+        constexpr int P = kSB == 1 ? kBoth : decltype(phase)::value;
+        const uint32_t off = (uint32_t)(blk - t0) / kSB;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            float mn = __builtin_fminf(__builtin_fminf(acc[g][0], acc[g][1]), acc[g][2]);
+            float mn;
+            if constexpr (P == kEnd) mn = __builtin_fminf(__builtin_fminf(carry[g], acc[g][0]), acc[g][1]);
+            else mn = __builtin_fminf(acc[g][0], acc[g][1]);
 #pragma unroll
-            for (int t = 3; t < 15; t += 2) mn = __builtin_fminf(__builtin_fminf(mn, acc[g][t]), acc[g][t + 1]);
-            mn = __builtin_fminf(mn, acc[g][15]);
-            const float key = __uint_as_float((__float_as_uint(mn) & vmask) | off);
-            sec[g] = __builtin_amdgcn_fmed3f(best[g], sec[g], key);
-            best[g] = __builtin_fminf(best[g], key);
+            for (int t = 2; t < 16; t += 2) mn = __builtin_fminf(__builtin_fminf(mn, acc[g][t]), acc[g][t + 1]);
+            if constexpr (P == kStart) {
+                carry[g] = mn;
+            } else {
+                const float key = __uint_as_float((__float_as_uint(mn) & vmask) | off);
+                sec[g] = __builtin_amdgcn_fmed3f(best[g], sec[g], key);
+                best[g] = __builtin_fminf(best[g], key);
+            }
         }
     };
+    const PhaseT<kStart> S_;
+    const PhaseT<kEnd> E_;
+    const PhaseT<kBoth> B_;
     // fragments of block blk, clamped into the range (loads past its end
     // re-read its last block). The second fragment of lane l + 32 meets
     // the queries' zero K slots 24..31, so it is read from lane l's
@@ -498,40 +525,40 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
             for (; b + 3 < t1; b += 4) {
                 products(fb0, fb1, accc);   // block b
                 frag(b + 4, fb0, fb1);
-                take_min(accp, b - 1);
+                take_min(accp, b - 1, S_);
                 __builtin_amdgcn_sched_barrier(0);
                 products(fc0, fc1, accp);   // block b + 1
                 frag(b + 5, fc0, fc1);
-                take_min(accc, b);
+                take_min(accc, b, E_);
                 __builtin_amdgcn_sched_barrier(0);
                 products(fd0, fd1, accc);   // block b + 2
                 frag(b + 6, fd0, fd1);
-                take_min(accp, b + 1);
+                take_min(accp, b + 1, S_);
                 __builtin_amdgcn_sched_barrier(0);
                 products(fa0, fa1, accp);   // block b + 3
                 frag(b + 7, fa0, fa1);
-                take_min(accc, b + 2);
+                take_min(accc, b + 2, E_);
                 __builtin_amdgcn_sched_barrier(0);
             }
             // zero to three blocks remain; accp holds block b - 1
             if (b < t1) {
                 products(fb0, fb1, accc);
-                take_min(accp, b - 1);
+                take_min(accp, b - 1, S_);
                 if (b + 1 < t1) {
                     products(fc0, fc1, accp);
-                    take_min(accc, b);
+                    take_min(accc, b, E_);
                     if (b + 2 < t1) {
                         products(fd0, fd1, accc);
-                        take_min(accp, b + 1);
-                        take_min(accc, b + 2);
+                        take_min(accp, b + 1, S_);
+                        take_min(accc, b + 2, E_);
                     } else {
-                        take_min(accp, b + 1);
+                        take_min(accp, b + 1, B_);
                     }
                 } else {
-                    take_min(accc, b);
+                    take_min(accc, b, E_);
                 }
             } else {
-                take_min(accp, b - 1);
+                take_min(accp, b - 1, B_);
             }
         }
     } else if constexpr (G >= 4) {
@@ -553,19 +580,19 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
                 // trip that consumed its buffer: two blocks of latency)
                 products(fb0, fb1, accc);   // block b
                 frag(b + 2, fb0, fb1);
-                take_min(accp, b - 1);
+                take_min(accp, b - 1, S_);
                 __builtin_amdgcn_sched_barrier(0);
                 products(fa0, fa1, accp);   // block b + 1
                 frag(b + 3, fa0, fa1);
-                take_min(accc, b);
+                take_min(accc, b, E_);
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (b < t1) {
                 products(fb0, fb1, accc);   // block b = t1 - 1
-                take_min(accp, b - 1);
-                take_min(accc, b);
+                take_min(accp, b - 1, S_);
+                take_min(accc, b, E_);
             } else {
-                take_min(accp, b - 1);
+                take_min(accp, b - 1, B_);
             }
         }
     } else {
@@ -581,16 +608,16 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
             for (; b + 1 < t1; b += 2) {
                 products(fa0, fa1, acc);   // block b
                 frag(b + 2, fa0, fa1);
-                take_min(acc, b);
+                take_min(acc, b, S_);
                 __builtin_amdgcn_sched_barrier(0);
                 products(fb0, fb1, acc);   // block b + 1
                 frag(b + 3, fb0, fb1);
-                take_min(acc, b + 1);
+                take_min(acc, b + 1, E_);
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (b < t1) {
                 products(fa0, fa1, acc);   // block b = t1 - 1
-                take_min(acc, b);
+                take_min(acc, b, B_);
             }
         }
     }
@@ -646,7 +673,7 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     };
 
     // The smallest key of each query over the workgroup's lanes. Only a lane
-    // whose best block could hold the query's chunk minimum reranks it: one
+    // whose best blocks could hold the query's chunk minimum reranks it: one
     // whose key, less the margin, is within the margin of that smallest key
     // (the lane holding it always does). The others certify all of their
     // blocks, the best included, from their best key below.
@@ -663,7 +690,7 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
         sm[0][jj] = m0;
     }
     __syncthreads();
-    uint32_t rerank = 0u;   // groups whose best block this lane reranks
+    uint32_t rerank = 0u;   // groups whose best blocks this lane reranks
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const float m = sm[0][32 * g + j];
@@ -676,23 +703,22 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
         }
     }
 
-    // exact FP32 rerank of the lane's sixteen references in its best block
-    // (keyed by the reference index), then the minimum over the two
-    // lanes of each query
+    // exact FP32 rerank of the lane's rows of its best key's blocks (16 kSB
+    // references, keyed by the reference index), then the minimum over the
+    // two lanes of each query
     const float4* __restrict__ rp = a.ref4 + pd.ref_off + c0;
     uint64_t key[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const float4 qf = qv[g];
-        const int32_t bblk = min(t0 + (int32_t)(__float_as_uint(best[g]) & ~kmask), t1 - 1);
-        const int64_t rb = (int64_t)bblk * kBlk;
+        const int32_t bblk = min(t0 + kSB * (int32_t)(__float_as_uint(best[g]) & ~kmask), t1 - 1);
         uint64_t k = ~0ull;
         if ((rerank >> g) & 1u) {
 #pragma unroll 4
-            for (int t = 0; t < 16; ++t) {
-                const int row = blk_row(t, h);
-                const float4 rr = rp[rb + row];
-                k = min(k, pack_key(dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z), (uint32_t)(c0 + rb + row)));
+            for (int t = 0; t < 16 * kSB; ++t) {
+                const int64_t r = (int64_t)min(bblk + (t >> 4), t1 - 1) * kBlk + blk_row(t & 15, h);
+                const float4 rr = rp[r];
+                k = min(k, pack_key(dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z), (uint32_t)(c0 + r)));
             }
         }
         k = min(k, (uint64_t)__shfl_xor((unsigned long long)k, 32));
@@ -829,7 +855,7 @@ __global__ __launch_bounds__(kWave) void screen_values_kernel(const PairDesc* __
 // one query per lane: four per SIMD.
 // BW: the launch may carry bandwidth workgroups (a separate instantiation,
 // so launches without them run the search's code alone).
-template <int Q, int W, int FMT, bool BW>
+template <int Q, int W, int FMT, bool BW, int SPAN>
 __global__ __launch_bounds__(kWave * W, Q == 1 ? 4 : 2) void nn_bf16_kernel(NNBf16Args a)
 {
     __shared__ uint64_t sk[W][kWave * Q];
@@ -840,7 +866,7 @@ __global__ __launch_bounds__(kWave * W, Q == 1 ? 4 : 2) void nn_bf16_kernel(NNBf
         return;
     }
     for (int64_t it = blockIdx.x - a.bw_blocks; it < a.nwork; it += gridDim.x - a.bw_blocks)
-        nn_bf16_item<Q, W, FMT>(a, a.work[it], sk, sm);
+        nn_bf16_item<Q, W, FMT, SPAN>(a, a.work[it], sk, sm);
 }
 
 }  // namespace sicp

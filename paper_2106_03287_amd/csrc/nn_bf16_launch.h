@@ -38,9 +38,18 @@ struct NNBf16Args {
 // wavefronts per workgroup (4, 8, 16 for one query per lane; 4, 8 for two).
 bool nn_bf16_shape_ok(int q, int w);
 
-// q, w as above; fmt: 0 the BF16 x 3 screen, 1 the FP16 x 2 screen; grid
-// workgroups (grid < nwork makes them persistent).
-hipError_t launch_nn_bf16_kernel(int q, int w, int fmt, unsigned grid, const NNBf16Args& a, hipStream_t s);
+// Blocks of 32 references per key for shape (q, w) when the shortest
+// chunk holds min_chunk references: 2 (q = 2 only) when every wavefront
+// sweeps at least 192 blocks per work item, else 1. A key over two blocks
+// takes 1.5 fewer vector instructions per block and query group and
+// doubles the rerank, which only long sweeps repay.
+int nn_bf16_key_span(int q, int w, int64_t min_chunk);
+
+// q, w as above; fmt: 0 the BF16 x 3 screen, 1 the FP16 x 2 screen; span:
+// blocks per key (1, or 2 for q = 2); grid workgroups (grid < nwork makes
+// them persistent).
+hipError_t launch_nn_bf16_kernel(int q, int w, int fmt, int span, unsigned grid, const NNBf16Args& a,
+                                 hipStream_t s);
 
 // FP16 screen scale exponent for a largest centred norm R (host copy of the
 // device rule).

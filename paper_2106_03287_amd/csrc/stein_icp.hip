@@ -332,7 +332,9 @@ hipError_t launch_nn_bf16(const Tiling& t, unsigned nwork, NNBf16Args a, int fmt
     if (t.w != 4 && t.w != 8 && t.w != 16) return hipErrorInvalidValue;
     a.nwork = nwork;
     const unsigned grid = t.persist > 0 ? std::min<unsigned>(nwork, (unsigned)(t.persist * g_num_cus)) : nwork;
-    return launch_nn_bf16_kernel(t.q, t.w, fmt, grid, a, s);
+    int64_t min_chunk = t.chunk.empty() ? 0 : INT64_MAX;
+    for (const int32_t c : t.chunk) min_chunk = std::min<int64_t>(min_chunk, c);
+    return launch_nn_bf16_kernel(t.q, t.w, fmt, nn_bf16_key_span(t.q, t.w, min_chunk), grid, a, s);
 }
 
 hipError_t launch_nn(const Tiling& t, unsigned nwork, NNArgs a, hipStream_t s)

@@ -589,6 +589,46 @@ def test_bf16_screen_every_block_count_per_wavefront(q, w, mode):
         sol.close()
 
 
+# the shortest chunk, in blocks of 32 references per wavefront, from which
+# the two-queries-per-lane screen keys two blocks at a time
+TWO_BLOCK_KEY_RANGE = 192
+
+
+@pytest.mark.parametrize("mode", SCREENS)
+@pytest.mark.parametrize("w", [4, 8])
+def test_screen_two_block_keys_every_block_count_per_wavefront(w, mode):
+    """With two queries per lane and chunks of at least 192 blocks per
+    wavefront, each key spans two blocks of 32 references. Reference clouds
+    of 1 to 89 blocks (ragged last blocks included) give the wavefronts 0 to
+    23 blocks each: odd and even counts, every tail of the block loops, a
+    last key of one block. The first iteration's matches equal the
+    oracle's (lowest index on ties), on the cuboid pair and on an all-ties
+    grid, and equal those of the one-block keys (a chunk one block
+    shorter)."""
+    prob = synth.make_problem("cuboid", 0, T=1)
+    gsrc, gref, gtheta, gsched, gK, gm, grows = _grid_problem()
+    long_chunk = 32 * w * TWO_BLOCK_KEY_RANGE
+    for nb in (1, 2, 3, 4, 5, 7, 8, 9, 13, 21, 34, 47, 55, 89):
+        for src, ref, theta0, sched, K, m, rows in (
+                (prob.pair.src, prob.pair.ref, prob.theta0, prob.schedule, prob.K, prob.m, prob.schedule.shape[0]),
+                (gsrc, gref, gtheta, gsched, gK, gm, grows)):
+            ref = ref[: max(1, 32 * nb - (nb % 3) * 7)]
+            cfg = S.stein_icp_default_config(num_particles=K, batch_size=m, schedule_rows=rows, autotune=0,
+                                             nn_mode=mode)
+            ocfg = oracle.make_config(K, m, len(src), len(ref))
+            want = oracle.step(ocfg, src, ref, sched[0], oracle.State(theta0))["match"]
+            sol = S.SteinICP(cfg, dev(src), dev(ref), dev(theta0), dev(sched))
+            try:
+                for chunk in (long_chunk, long_chunk - 32):
+                    sol.set_tiling(2, w, chunk)
+                    sol.set_state(dev(theta0))
+                    sol.step(1)
+                    got = sol.diagnostics()["match"].cpu().numpy()[0]
+                    assert np.array_equal(got, want), (w, nb, len(ref), chunk, int((got != want).sum()))
+            finally:
+                sol.close()
+
+
 def test_bf16_solver_equals_the_fp32_solver_bitwise():
     """With the certified screen the matches are the FP32 search's, so the
     whole solve is bit for bit the FP32 solve (and the first iteration's
