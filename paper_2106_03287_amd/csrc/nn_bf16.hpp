@@ -742,10 +742,11 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
     // has its own rows of its own blocks (16 (t1 - t0) references) searched
     // again in FP32 by its wavefront, folded into the chunk minimum in LDS
     if (t0 < t1) {
-        const int64_t nref = 16 * (t1 - t0);
         // gathers kept in flight together (one query per lane: the
-        // unrolled loop's registers would cost occupancy)
-        constexpr int kRescanUnroll = Q == 1 ? 1 : 4;
+        // unrolled loop's registers would cost occupancy; measured best:
+        // eight for FP16 x 2, four for BF16 x 3)
+        constexpr int kRescanUnroll = Q == 1 ? 1 : (F16 ? 8 : 4);
+        const int32_t ntrip = (t1 - t0 + 3) >> 2;   // four blocks per trip
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int64_t qi = qbase + 32 * g + j;
@@ -767,12 +768,20 @@ __device__ __forceinline__ void nn_bf16_item(const NNBf16Args& a, const WorkItem
                 mask &= mask - 1ull;
                 const int fj = b & 31, fh = b >> 5;
                 const float4 qf = a.queries[pd.q_off + qbase + 32 * g + fj];
+                // lane l takes row blk_row(l % 16, fh) of blocks t0 + l / 16,
+                // t0 + l / 16 + 4, ...: a fixed row per lane, the wavefront
+                // four blocks per trip; past the range a lane reads the
+                // range's last block again (a duplicate leaves the minimum
+                // unchanged), so the gathers carry no branch
+                const int32_t lb = t0 + (lane >> 4);
+                const int64_t rrow = c0 + blk_row(lane & 15, fh);
+                const float4* __restrict__ rq = a.ref4 + pd.ref_off + rrow;
                 uint64_t kr = ~0ull;
 #pragma unroll kRescanUnroll
-                for (int64_t e = lane; e < nref; e += kWave) {
-                    const int64_t r = c0 + (t0 + e / 16) * kBlk + blk_row((int)(e & 15), fh);
-                    const float4 rr = a.ref4[pd.ref_off + r];
-                    kr = min(kr, pack_key(dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z), (uint32_t)r));
+                for (int32_t it = 0; it < ntrip; ++it) {
+                    const int64_t bo = (int64_t)min(lb + 4 * it, t1 - 1) * kBlk;
+                    const float4 rr = rq[bo];
+                    kr = min(kr, pack_key(dist2_f32(qf.x, qf.y, qf.z, rr.x, rr.y, rr.z), (uint32_t)(rrow + bo)));
                 }
 #pragma unroll
                 for (int o = kWave / 2; o > 0; o >>= 1) kr = min(kr, (uint64_t)__shfl_xor((unsigned long long)kr, o));
