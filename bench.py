@@ -118,6 +118,17 @@ def measured_counters(workload, tiling, nn="fp32"):
     return rec
 
 
+CEILINGS = {}   # the device's own ceilings, measured once per run (paper_2106_03287_amd.peaks)
+
+
+def measure_ceilings():
+    """Streaming copy, unpacked FP32 FMA and 32x32x16 FP16 / BF16 matrix-core
+    rates of this device, best of five probes each, before any timed region."""
+    from paper_2106_03287_amd import peaks
+    CEILINGS.update(peaks.measure())
+    return {k: (round(v, 1) if isinstance(v, float) else v) for k, v in CEILINGS.items()}
+
+
 def nn_roofline(nn, pairs_per_launch, nn_ms, counters):
     """Roofline of the dominant kernel, the nearest-neighbour search: the
     algorithmic 8 flops per pair evaluation over the launch time, against
@@ -143,6 +154,15 @@ def nn_roofline(nn, pairs_per_launch, nn_ms, counters):
     else:
         out.update(bound="alu", peak=VALU_PEAK_TFLOPS, frac=round(useful / VALU_PEAK_TFLOPS, 4),
                    kernel="nn_fp32_kernel")
+    if CEILINGS:
+        # the same achieved rate against the ceiling this device sustains for
+        # the kernel's arithmetic (the build has no packed FP32 instructions,
+        # so the FP32 search's ceiling is the unpacked FMA rate)
+        key = {"f16": "mfma_f16_tflops", "bf16": "mfma_bf16_tflops"}.get(nn, "fp32_fma_tflops")
+        out["measured_peak"] = {"value": round(CEILINGS[key], 1), "unit": "TFLOP/s", "probe": key,
+                                "frac": round(useful / CEILINGS[key], 4)}
+        if traffic is not None:
+            out["hbm_frac_of_measured_copy"] = round(traffic / t / 1e9 / CEILINGS["hbm_copy_gbps"], 4)
     order = ["bound", "achieved", "peak", "unit", "frac", "traffic"]
     return {k: out[k] for k in order + sorted(k for k in out if k not in order)}
 
@@ -219,6 +239,9 @@ def main():
                     help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--iters", type=int, default=0,
                     help="iterations per solve (default: the workload's T); for short profiled runs")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip measuring the device's own copy / FMA / matrix-core ceilings (skipped anyway "
+                         "with --iters, the short profiled runs)")
     ap.add_argument("--tiling", default="",
                     help="force the NN shape 'queries_per_lane,waves,chunk[,persist]' instead of tuning")
     args = ap.parse_args()
@@ -232,6 +255,9 @@ def main():
     import synth
     from paper_2106_03287_amd import stein_icp as S
 
+    args.ceilings = None
+    if not args.no_ceilings and not args.iters:
+        args.ceilings = measure_ceilings()
     if args.nn == "auto":
         args.nn = AUTO_NN.get(args.workload, "fp32")
     if not args.tiling and not args.autotune:
@@ -362,6 +388,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, plane=args.metric == "plane")
     out["host"] = gpu_info(args.host)
+    out["device_ceilings"] = args.ceilings
     print(json.dumps(out), flush=True)
 
 
@@ -454,6 +481,7 @@ def run_batched(args):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batched(probs, T)
     out["host"] = gpu_info(args.host)
+    out["device_ceilings"] = args.ceilings
     print(json.dumps(out), flush=True)
 
 
@@ -568,6 +596,7 @@ def run_mc(args):
     mc.close()
     stein.close()
     out["host"] = gpu_info(args.host)
+    out["device_ceilings"] = args.ceilings
     print(json.dumps(out), flush=True)
 
 
@@ -691,10 +720,15 @@ def run_proposal(args):
                      "kernel": "proposal forward (all kernels)",
                      "flops_per_pair": 2 * PROPOSAL_MACS_PER_PAIR, "avg_ms_per_pair": round(net_ms / n, 5)},
     }
+    if CEILINGS:
+        out["roofline"]["measured_peak"] = {"value": round(CEILINGS["mfma_bf16_tflops"], 1), "unit": "TFLOP/s",
+                                            "probe": "mfma_bf16_tflops",
+                                            "frac": round(achieved / CEILINGS["mfma_bf16_tflops"], 4)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_proposal(ds, res, T)
     model.close()
     out["host"] = gpu_info(args.host)
+    out["device_ceilings"] = args.ceilings
     print(json.dumps(out), flush=True)
 
 

@@ -14,6 +14,7 @@ SOURCES = [
     (os.path.join(HERE, "stein_icp.hip"), []),
     (os.path.join(HERE, "nn_bf16.hip"), ["-fno-honor-nans", "-mno-amdgpu-ieee"]),
     (os.path.join(HERE, "proposal.hip"), []),
+    (os.path.join(HERE, "peaks.hip"), []),
 ]
 OUT = os.path.join(PKG, "libstein_icp.so")
 

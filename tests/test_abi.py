@@ -152,3 +152,23 @@ def test_library_initial_particles_are_uniform_in_the_box():
         S.stein_icp_make_init(5, 0, 0.2, 0.1)
     with pytest.raises(S.SteinICPError):
         S.stein_icp_make_schedule(5, 10, 11, 1)
+
+
+def test_peak_probes_are_exported_and_validate_before_launching():
+    from paper_2106_03287_amd import peaks as P
+    text = open(os.path.join(ROOT, "include", "stein_icp_peaks.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    declared = sorted(set(re.findall(r"\b(stein_icp_[a-z_0-9]+)\s*\(", text)))
+    L = P.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(P.EXPORTS) == declared
+    fake = C.c_void_p(16)   # never dereferenced: every case fails validation
+    for kind, n, iters in ((7, 256, 1), (-1, 256, 1), (P.PEAK_COPY, 0, 1), (P.PEAK_FMA32, 100, 1),
+                           (P.PEAK_MFMA_F16, 256, 0), (P.PEAK_MFMA_BF16, 256, (1 << 24) + 1)):
+        assert L.stein_icp_peak_probe(kind, fake, fake, n, iters, 1.0, 1.0, None) == S.E_INVALID
+    assert L.stein_icp_peak_probe(P.PEAK_COPY, None, fake, 16, 1, 1.0, 1.0, None) == S.E_INVALID
+    assert P.peak_work(P.PEAK_COPY, 1000) == 32000.0
+    assert P.peak_work(P.PEAK_FMA32, 256, 10) == 2 * 16 * 256 * 10
+    assert P.peak_work(P.PEAK_MFMA_F16, 256, 3) == 4 * 4 * 2 * 32 * 32 * 16 * 3
+    assert P.peak_work(9, 1, 1) < 0
