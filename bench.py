@@ -242,6 +242,9 @@ def main():
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip measuring the device's own copy / FMA / matrix-core ceilings (skipped anyway "
                          "with --iters, the short profiled runs)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched workload: skip the same pairs solved one after another (counter runs, whose "
+                         "kernel records should hold the batched launches only)")
     ap.add_argument("--tiling", default="",
                     help="force the NN shape 'queries_per_lane,waves,chunk[,persist]' instead of tuning")
     args = ap.parse_args()
@@ -264,13 +267,6 @@ def main():
         args.tiling = PINNED_TILING.get((args.workload, args.nn), "")
         if not args.tiling:
             args.autotune = 1
-    if args.workload == "batched":
-        return run_batched(args)
-    if args.workload == "proposal":
-        return run_proposal(args)
-    if args.workload == "mc":
-        return run_mc(args)
-
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -279,6 +275,12 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.workload == "batched":
+        return run_batched(args)
+    if args.workload == "proposal":
+        return run_proposal(args)
+    if args.workload == "mc":
+        return run_mc(args)
 
     prob = synth.make_problem(args.workload, 0)
     if args.iters:
@@ -418,7 +420,8 @@ def run_batched(args):
         batch.set_tiling(*[int(x) for x in args.tiling.split(",")])
     tiling = batch.tiling()
     zeros = torch.zeros_like(th0)
-    singles = [S.SteinICP(cfg, srcs[i], refs[i], th0[i].contiguous(), scheds[i]) for i in range(P)]
+    singles = [] if args.no_sequential else [S.SteinICP(cfg, srcs[i], refs[i], th0[i].contiguous(), scheds[i])
+                                             for i in range(P)]
     z1 = torch.zeros_like(th0[0])
 
     def solve_batched():
@@ -441,8 +444,10 @@ def run_batched(args):
         return (time.perf_counter() - t0) * 1e3 / steps
 
     ms_b = timed(solve_batched, args.steps, args.warmup)
-    ms_s = timed(solve_sequential, max(1, args.steps // 2), 1)
-    same = bool(torch.equal(batch.particles(), torch.stack([s.particles()[0] for s in singles])))
+    ms_s, same = None, None
+    if singles:
+        ms_s = timed(solve_sequential, max(1, args.steps // 2), 1)
+        same = bool(torch.equal(batch.particles(), torch.stack([s.particles()[0] for s in singles])))
     S.stein_icp_set_state(batch.ctx, th0, zeros, zeros, 0)
     stage = batch.stage_times(T)
     nn_ms = batch.time_nn(20)
@@ -466,9 +471,9 @@ def run_batched(args):
                    "M_range": [min(len(p.pair.ref) for p in probs), max(len(p.pair.ref) for p in probs)],
                    "N_range": [min(len(p.pair.src) for p in probs), max(len(p.pair.src) for p in probs)],
                    "nn": args.nn, "step": "one batched solve of all pairs, T iterations"},
-        "sequential_ms": round(ms_s, 3),
-        "sequential_pair_iters_per_s": round(P * T / (ms_s / 1e3), 2),
-        "speedup_vs_sequential": round(ms_s / ms_b, 3),
+        "sequential_ms": None if ms_s is None else round(ms_s, 3),
+        "sequential_pair_iters_per_s": None if ms_s is None else round(P * T / (ms_s / 1e3), 2),
+        "speedup_vs_sequential": None if ms_s is None else round(ms_s / ms_b, 3),
         "batched_equals_sequential_bitwise": same,
         "stage_ms_per_iter": {k: round(v / T, 5) for k, v in stage.items()},
         "init_ms": round(init_ms, 2),

@@ -391,8 +391,10 @@ void build_work(stein_icp_ctx* c)
     }
     // chunk-major order inside a group so neighbouring workgroups (which the
     // dispatcher spreads round-robin over the eight XCDs) read different
-    // chunks of the same queries; every reference array here fits each
-    // XCD's L2, so locality across XCDs is not the limiter.
+    // chunks of the same queries: with two chunks, XCD x always searches
+    // chunk x mod 2. Many pairs' fragments together exceed an XCD's L2
+    // (each XCD then fills every pair's once per launch), but the search
+    // stays far from the HBM bound there.
     for (int32_t gi = 0; gi < (int32_t)c->groups.size(); ++gi) {
         const PairDesc& g = c->groups[gi];
         for (int32_t b = 0; b < g.qblocks; ++b)
