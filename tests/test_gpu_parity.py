@@ -366,8 +366,9 @@ def test_bandwidth_selection_degenerate_particle_sets(kind):
     _one_step_compare(prob)
 
 
-@pytest.mark.parametrize("K", [120, 300])
-@pytest.mark.parametrize("kind", ["uniform", "identical", "two_clusters", "near_duplicates", "few_values"])
+@pytest.mark.parametrize("K,kind", [(K, kind) for K in (120, 300)
+                                    for kind in ("uniform", "identical", "two_clusters", "near_duplicates",
+                                                 "few_values")] + [(133, "uniform"), (134, "uniform")])
 def test_bandwidths_beside_the_screen_search_equal_the_gradient_launch(kind, K):
     """With a screen and few particles in flight the median bandwidths run
     as extra workgroups of the nearest-neighbour launch, on its workgroup
@@ -375,7 +376,9 @@ def test_bandwidths_beside_the_screen_search_equal_the_gradient_launch(kind, K):
     search, 1024 threads) bit for bit and the oracle's, and the iteration's
     particles are the same, on degenerate particle sets too. K = 120 keeps
     the pair keys in LDS there; K = 300 (the LiDAR particle count) keeps the
-    distances in global memory there, while the gradient launch keys them."""
+    distances in global memory there, while the gradient launch keys them.
+    K = 133 is the largest K whose keys fit the 48 KB there, K = 134 the
+    smallest that takes global memory."""
     prob = synth.make_problem("cuboid", 13, K=K, T=2)
     if kind != "uniform":
         prob.theta0 = _theta_variant(prob, kind, np.random.default_rng(5))
