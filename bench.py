@@ -150,7 +150,8 @@ def nn_roofline(nn, pairs_per_launch, nn_ms, counters):
                    kernel="nn_bf16_kernel (%s)" % ("BF16 x 3" if nn == "bf16" else "FP16 x 2"),
                    issued_mfma={"flops_per_pair": per, "achieved": round(issued, 3),
                                 "frac": round(issued / MFMA_BF16_PEAK_TFLOPS, 4)},
-                   mfma_busy=counters.get("mfma_busy"))
+                   mfma_busy=counters.get("mfma_busy"), valu_busy=counters.get("valu_busy"),
+                   valu_insts_per_mfma=counters.get("valu_insts_per_mfma"))
     else:
         out.update(bound="alu", peak=VALU_PEAK_TFLOPS, frac=round(useful / VALU_PEAK_TFLOPS, 4),
                    kernel="nn_fp32_kernel")
