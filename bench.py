@@ -193,6 +193,103 @@ def cpu_baseline(prob, budget_s=15.0, plane=False):
                       f"the T={prob.T} solve"}
 
 
+class KDTreeReference:
+    """A fast CPU form of the iteration for context beside the oracle (not the
+    oracle, and not the product): the nearest neighbours of the FP32 queries
+    from a scipy cKDTree over the reference (the oracle's threads, distances in
+    FP64, so a near-tie may match differently from the FP32 search), the rest
+    vectorised in NumPy FP64 as the method states it: minibatch row t mod
+    rows, the pose R = Rz(yaw) Ry(pitch) Rx(roll) and its derivatives, the
+    mean gradient of Eqs. 4-5, the Stein direction of Eq. 16 with the
+    wrapped-angle kernel of Eq. 17 and median-heuristic bandwidths, Adam on
+    the negative direction (Sec. V)."""
+
+    def __init__(self, prob, beta1=0.9, beta2=0.999, eps=1e-8):
+        from scipy.spatial import cKDTree
+        self.src = np.asarray(prob.pair.src, np.float32)
+        self.ref = np.asarray(prob.pair.ref, np.float32).astype(np.float64)
+        self.tree = cKDTree(self.ref)
+        self.workers = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))   # the oracle's threads
+        self.sched = np.asarray(prob.schedule)
+        self.K, self.m, self.N, self.lr = prob.K, prob.m, len(prob.pair.src), prob.lr
+        self.b1, self.b2, self.eps = beta1, beta2, eps
+        self.theta = np.array(prob.theta0, np.float64)
+        self.mom = np.zeros_like(self.theta)
+        self.vel = np.zeros_like(self.theta)
+        self.t = 0
+
+    @staticmethod
+    def _wrap(x):
+        return x - np.rint(x / (2 * np.pi)) * (2 * np.pi)
+
+    @staticmethod
+    def _pose(th):
+        cr, sr = np.cos(th[:, 3]), np.sin(th[:, 3])
+        cp, sp = np.cos(th[:, 4]), np.sin(th[:, 4])
+        cy, sy = np.cos(th[:, 5]), np.sin(th[:, 5])
+        z, o = np.zeros_like(cr), np.ones_like(cr)
+        Rx = np.stack([o, z, z, z, cr, -sr, z, sr, cr], 1).reshape(-1, 3, 3)
+        Ry = np.stack([cp, z, sp, z, o, z, -sp, z, cp], 1).reshape(-1, 3, 3)
+        Rz = np.stack([cy, -sy, z, sy, cy, z, z, z, o], 1).reshape(-1, 3, 3)
+        dRx = np.stack([z, z, z, z, -sr, -cr, z, cr, -sr], 1).reshape(-1, 3, 3)
+        dRy = np.stack([-sp, z, cp, z, z, z, -cp, z, -sp], 1).reshape(-1, 3, 3)
+        dRz = np.stack([-sy, -cy, z, cy, -sy, z, z, z, z], 1).reshape(-1, 3, 3)
+        R = Rz @ Ry @ Rx
+        return R, np.stack([Rz @ Ry @ dRx, Rz @ dRy @ Rx, dRz @ Ry @ Rx], 1)
+
+    def step(self):
+        K, m = self.K, self.m
+        s = self.src[self.sched[self.t % len(self.sched)]].astype(np.float64)          # m x 3
+        R, D = self._pose(self.theta)
+        q = np.einsum("kij,mj->kmi", R, s) + self.theta[:, None, :3]                     # K x m x 3
+        _, j = self.tree.query(q.astype(np.float32).reshape(-1, 3).astype(np.float64), workers=self.workers)
+        e = q - self.ref[j].reshape(K, m, 3)
+        g = np.empty((K, 6))
+        g[:, :3] = e.mean(1)
+        g[:, 3:] = np.einsum("kmi,kdij,mj->kd", e, D, s, optimize=True) / m
+        dt = self.theta[:, None, :3] - self.theta[None, :, :3]                            # l, k
+        dr = self._wrap(self.theta[:, None, 3:] - self.theta[None, :, 3:])
+        d2 = [(dt ** 2).sum(-1), (dr ** 2).sum(-1)]
+        iu = np.triu_indices(K, 1)
+        G = -self.N * g
+        phi = np.zeros((K, 6))
+        for b, diff in enumerate((dt, dr)):
+            if K > 1:
+                v = np.sort(d2[b][iu])
+                n = len(v)
+                med = np.sqrt(v[(n - 1) // 2]) if n % 2 else 0.5 * (np.sqrt(v[n // 2 - 1]) + np.sqrt(v[n // 2]))
+                h = med * med / np.log(K) if med > 0 else 1.0
+            else:
+                h = 1.0
+            kern = np.exp(-d2[b] / h)
+            sl = slice(3 * b, 3 * b + 3)
+            phi[:, sl] = (kern.T @ G[:, sl] + (-2.0 / h) * np.einsum("lk,lkd->kd", kern, diff)) / K
+        self.t += 1
+        gr = -phi
+        self.mom = self.b1 * self.mom + (1 - self.b1) * gr
+        self.vel = self.b2 * self.vel + (1 - self.b2) * gr * gr
+        mh = self.mom / (1 - self.b1 ** self.t)
+        vh = self.vel / (1 - self.b2 ** self.t)
+        self.theta = self.theta - self.lr * mh / (np.sqrt(vh) + self.eps)
+        return j
+
+
+def cpu_kdtree_reference(prob, budget_s=10.0):
+    """KDTreeReference timed on this host for about ``budget_s`` seconds."""
+    ref = KDTreeReference(prob)
+    ref.step()   # warm-up
+    t0 = time.perf_counter()
+    n = 0
+    while n < prob.T - 1 and (n == 0 or time.perf_counter() - t0 < budget_s):
+        ref.step()
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "iters/s", "cores": ref.workers,
+            "kind": "scipy cKDTree nearest neighbours + NumPy FP64 (a fast CPU form, not the oracle)",
+            "sample": f"iterations 2-{n + 1} of the {prob.name} workload (K={prob.K}, m={prob.m}, "
+                      f"M={len(prob.pair.ref)}), the tree built outside the timing"}
+
+
 # Search mode of --nn auto. The certified screens return the FP32 search's
 # answers bit for bit. The FP16 x 2 screen (one matrix product per block)
 # measured faster than the BF16 x 3 screen (two) on the NN launch: LiDAR
@@ -390,6 +487,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, plane=args.metric == "plane")
+        if args.metric == "point":
+            out["cpu_fast_reference"] = cpu_kdtree_reference(prob)
     out["host"] = gpu_info(args.host)
     out["device_ceilings"] = args.ceilings
     print(json.dumps(out), flush=True)
