@@ -16,20 +16,21 @@
 // wavefront). Lane l owns query l % 32 of each group and receives rows
 // 8 i + 4 (l / 32) + 0..3 (i = 0..3) of each 32-reference block; it keeps
 // only a key of the minimum of those sixteen values per block, or per two
-// blocks (see the certificate below). The
-// wide product gives each lane sixteen values to reduce per pair of matrix
-// instructions (three-input minimums), where a 16 x 16 product gives four
-// per instruction: the vector-ALU work per distance, which bounded a 16 x 16
-// screen, about halves.
+// blocks (see the certificate below). The wide product gives each lane
+// sixteen values to reduce per pair of matrix instructions (three-input
+// minimums), where a 16 x 16 product gives four per instruction: the
+// vector-ALU work per distance, which bounded a 16 x 16 screen, about
+// halves.
 //
 // Rerank: the workgroup first finds each query's smallest key over its
 // lanes; a lane whose best key, less the error margin, is within the margin
 // of it (the lane holding it always is) recomputes the exact FP32 distance
 // (the same operation sequence as the FP32 search) of its rows of its best
 // key's blocks, keyed by the reference index; the two lanes of a query
-// merge their (distance, index) keys. The FP32 search keys by 16-reference tile instead;
-// both order by distance, then lowest index, so the chunk reduction is
-// shared, and an index key needs no tile resolution downstream.
+// merge their (distance, index) keys. The FP32 search keys by 16-reference
+// tile instead; both order by distance, then lowest index, so the chunk
+// reduction is shared, and an index key needs no tile resolution
+// downstream.
 //
 // Certificate: the result is the FP32 search's exact chunk minimum, ties
 // included. Let S be the screened and F the FP32 distance of a reference.
@@ -48,10 +49,9 @@
 // (s2; for a lane that did not rerank, the best key bounds all of its
 // blocks). After the workgroup merges its keys into the chunk minimum F_wg,
 // a lane whose references outside its reranked blocks all satisfy F > F_wg
-// -- guaranteed
-// when s2 - 60 u (|q_c| + R')^2 > F_wg (1 + 8 u)
-// with R' = min(R, |q_c| + sqrt(F_wg)), as only references within sqrt(F_wg)
-// of the query can win -- has lost nothing; otherwise that lane's own rows
+// (guaranteed when s2 - 60 u (|q_c| + R')^2 > F_wg (1 + 8 u) with
+// R' = min(R, |q_c| + sqrt(F_wg)), as only references within sqrt(F_wg) of
+// the query can win) has lost nothing; otherwise that lane's own rows
 // of its wavefront's blocks are searched again in FP32 by the wavefront and
 // folded into the chunk minimum. The result is the FP32 search's key, ties
 // included.
