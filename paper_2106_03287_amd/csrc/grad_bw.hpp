@@ -16,7 +16,7 @@ static_assert(kGradGroups * kGradThreads == kSvgdThreads, "both roles use the sa
 inline size_t grad_bw_lds_bytes(int K)
 {
     const size_t sel = (sizeof(SelectShared) + 15) / 16 * 16;
-    const size_t bw = sel + bandwidth_lds_bytes(K, bandwidth_keyable(K));
+    const size_t bw = sel + bandwidth_lds_bytes(K, bandwidth_keyable(K) ? kKeysInLds : kDistancesInGlobal);
     const size_t gr = sizeof(double) * 6 * kGradGroups * (kGradThreads / kWave);
     return bw > gr ? bw : gr;
 }
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(kSvgdThreads) void grad_bandwidth_kernel(GradArgs g
     extern __shared__ double lds[];
     const int64_t bw_blocks = 2 * (int64_t)bw_pairs;
     if ((int64_t)blockIdx.x < bw_blocks) {   // whole workgroup
-        bandwidth_role<kSvgdThreads>(v, blockIdx.x, bandwidth_keyable(v.K), lds);
+        bandwidth_role<kSvgdThreads>(v, blockIdx.x, bandwidth_keyable(v.K) ? kKeysInLds : kDistancesInGlobal, lds);
         return;
     }
     const int64_t wg = (int64_t)blockIdx.x - bw_blocks;

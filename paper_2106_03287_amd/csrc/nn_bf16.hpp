@@ -871,7 +871,7 @@ __global__ __launch_bounds__(kWave * W, Q == 1 ? 4 : 2) void nn_bf16_kernel(NNBf
     __shared__ float sm[W][kWave * Q];
     if (BW && (int)blockIdx.x < a.bw_blocks) {
         extern __shared__ double bw_lds[];
-        bandwidth_role<kWave * W>(a.bw, blockIdx.x, a.bw_keyed != 0, bw_lds);
+        bandwidth_role<kWave * W>(a.bw, blockIdx.x, a.bw_form, bw_lds);
         return;
     }
     for (int64_t it = blockIdx.x - a.bw_blocks; it < a.nwork; it += gridDim.x - a.bw_blocks)

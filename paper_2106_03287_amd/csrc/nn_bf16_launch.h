@@ -26,12 +26,12 @@ struct NNBf16Args {
     unsigned long long* rescans;   // if set: certificates that failed, accumulated
     // bw_blocks > 0: the launch's first bw_blocks workgroups compute the
     // iteration's median-heuristic bandwidths instead (bw_lds bytes of
-    // dynamic LDS each; bw_keyed: pair keys in LDS, else FP64 distances in
-    // global memory), beside the search
+    // dynamic LDS each; bw_form: where the pair distances go, a
+    // BandwidthForm), beside the search
     SvgdArgs bw;
     int32_t bw_blocks;
     uint32_t bw_lds;
-    int32_t bw_keyed;
+    int32_t bw_form;
 };
 
 // Shapes the screen is built for: q queries per lane (1 or 2) and w

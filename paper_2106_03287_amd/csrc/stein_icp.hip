@@ -226,17 +226,20 @@ bool const_bandwidth(const stein_icp_config& c)
 constexpr size_t kFusedBandwidthLds = 48 * 1024;
 int g_num_cus = 256;   // compute units of the device, read at the first init
 
-// Whether the fused bandwidth workgroups keep the pair keys in LDS.
-bool fused_bandwidth_keyed(int K)
+// Where the fused bandwidth workgroups keep the pair distances: keys in LDS
+// where they fit, else keys in global memory (the keyed selection reads a
+// quarter of the bytes of FP64 distances, in fewer passes), else FP64.
+int fused_bandwidth_form(int K)
 {
-    return bandwidth_keyable(K) && bandwidth_role_lds_bytes(K, true) <= kFusedBandwidthLds;
+    if (!bandwidth_keyable(K)) return kDistancesInGlobal;
+    return bandwidth_role_lds_bytes(K, kKeysInLds) <= kFusedBandwidthLds ? kKeysInLds : kKeysInGlobal;
 }
 
 bool fused_bandwidth(const stein_icp_config& c, int64_t pairs)
 {
     const int K = c.num_particles;
     return is_screen(c.nn_mode) && !const_bandwidth(c) &&
-           bandwidth_role_lds_bytes(K, fused_bandwidth_keyed(K)) <= kFusedBandwidthLds &&
+           bandwidth_role_lds_bytes(K, fused_bandwidth_form(K)) <= kFusedBandwidthLds &&
            pairs * K <= 2 * (int64_t)g_num_cus;
 }
 
@@ -508,8 +511,8 @@ hipError_t enqueue_stage(const stein_icp_ctx* c, int stage, hipStream_t s)
             if (fused_bandwidth(c->cfg, c->P)) {
                 b.bw = svgd_args(c);
                 b.bw_blocks = 2 * c->P;
-                b.bw_keyed = fused_bandwidth_keyed(c->K) ? 1 : 0;
-                b.bw_lds = (uint32_t)bandwidth_role_lds_bytes(c->K, b.bw_keyed != 0);
+                b.bw_form = fused_bandwidth_form(c->K);
+                b.bw_lds = (uint32_t)bandwidth_role_lds_bytes(c->K, b.bw_form);
             }
             return launch_nn_bf16(c->tiling, (unsigned)c->work.size(), b, screen_fmt(c->cfg.nn_mode), s);
         }

@@ -30,7 +30,7 @@ struct SvgdArgs {
     const double* gbar;
     double* phi;
     double* h;            // 2 per pair
-    double* dscr;         // K(K-1)/2 per pair and block, for K above the keyed limit
+    double* dscr;         // K(K-1)/2 per pair and block: the pair distances or keys in global memory
     Pose* pose;
     const float4* src4;
     const int32_t* sched;
@@ -584,18 +584,23 @@ __device__ inline void select_pair_keyed(const uint16_t* key, int64_t n, int64_t
 // to this many pairs (K up to about 345); beyond, as FP64 in global memory.
 constexpr int64_t kMaxKeyedPairs = 60000;
 
-// Whether bandwidth_body may keep the pair keys of K particles in LDS.
+// Whether bandwidth_body may select over the 16-bit pair keys of K particles.
 __host__ __device__ inline bool bandwidth_keyable(int K) { return (int64_t)K * (K - 1) / 2 <= kMaxKeyedPairs; }
+
+// Where bandwidth_body keeps the pair distances: 16-bit keys in LDS, 16-bit
+// keys in global memory (the `dscr` scratch), or FP64 distances in global
+// memory. All three find the same exact order statistics.
+enum BandwidthForm : int32_t { kKeysInLds = 0, kKeysInGlobal = 1, kDistancesInGlobal = 2 };
 
 // grid (pairs, 2), 1024 threads. blockIdx.y: 0 translation, 1 rotation.
 // Dynamic LDS: K x 6 particles (FP64) followed by the 16-bit pair keys.
 // Median-heuristic bandwidth of pair p, block rot (0 translation, 1
 // rotation), by one NT-thread workgroup; `sh` and `dyn`
-// (bandwidth_lds_bytes(K, keyed)) are the workgroup's LDS. `keyed` (only
-// where bandwidth_keyable(K)): the pair distances go to LDS as 16-bit keys,
-// else to global memory as FP64; both find the same exact order statistics.
+// (bandwidth_lds_bytes(K, form)) are the workgroup's LDS. `form`
+// (BandwidthForm; the key forms only where bandwidth_keyable(K)) places the
+// pair distances.
 template <int NT>
-__device__ __forceinline__ void bandwidth_body(const SvgdArgs& a, int64_t p, int rot, bool keyed, SelectShared& sh,
+__device__ __forceinline__ void bandwidth_body(const SvgdArgs& a, int64_t p, int rot, int form, SelectShared& sh,
                                                double* dyn)
 {
     const int K = a.K;
@@ -610,8 +615,9 @@ __device__ __forceinline__ void bandwidth_body(const SvgdArgs& a, int64_t p, int
     const int64_t np = (int64_t)K * (K - 1) / 2;
     const int64_t ra = (np - 1) / 2, rb = np / 2;
     double va, vb;
-    if (keyed) {
-        uint16_t* key = reinterpret_cast<uint16_t*>(dyn + 6 * K);
+    if (form != kDistancesInGlobal) {
+        uint16_t* key = form == kKeysInLds ? reinterpret_cast<uint16_t*>(dyn + 6 * K)
+                                           : reinterpret_cast<uint16_t*>(a.dscr + (p * 2 + rot) * np);
         // the keys, their range (per wavefront) and the cleared histogram
         // of the selection, under one barrier
         uint32_t kmin = 0xffffu, kmax = 0u;
@@ -625,6 +631,7 @@ __device__ __forceinline__ void bandwidth_body(const SvgdArgs& a, int64_t p, int
             }
         }
         select_pair_prologue<NT>(kmin, kmax, sh);
+        if (form == kKeysInGlobal) __threadfence_block();
         __syncthreads();
         select_pair_keyed<NT>(key, np, ra, rb, K, rot, th, sh, va, vb);
     } else {
@@ -647,29 +654,29 @@ __device__ __forceinline__ void bandwidth_body(const SvgdArgs& a, int64_t p, int
 }
 
 // LDS bytes of bandwidth_body besides SelectShared.
-inline size_t bandwidth_lds_bytes(int K, bool keyed)
+inline size_t bandwidth_lds_bytes(int K, int form)
 {
     const int64_t np = (int64_t)K * (K - 1) / 2;
     size_t b = 48 * (size_t)K;
-    if (keyed) b += 2 * (size_t)np;
+    if (form == kKeysInLds) b += 2 * (size_t)np;
     return (b + 15) / 16 * 16;
 }
 
 // Dynamic LDS bytes of a bandwidth workgroup (SelectShared, then the
 // particles and keys of bandwidth_body).
-inline size_t bandwidth_role_lds_bytes(int K, bool keyed)
+inline size_t bandwidth_role_lds_bytes(int K, int form)
 {
-    return (sizeof(SelectShared) + 15) / 16 * 16 + bandwidth_lds_bytes(K, keyed);
+    return (sizeof(SelectShared) + 15) / 16 * 16 + bandwidth_lds_bytes(K, form);
 }
 
 // Bandwidth workgroup b of a launch (pair b / 2, block b % 2) on NT threads;
-// lds: its dynamic LDS of bandwidth_role_lds_bytes(K, keyed) bytes.
+// lds: its dynamic LDS of bandwidth_role_lds_bytes(K, form) bytes.
 template <int NT>
-__device__ __forceinline__ void bandwidth_role(const SvgdArgs& v, int64_t b, bool keyed, double* lds)
+__device__ __forceinline__ void bandwidth_role(const SvgdArgs& v, int64_t b, int form, double* lds)
 {
     SelectShared& sh = *reinterpret_cast<SelectShared*>(lds);
     double* dyn = lds + (sizeof(SelectShared) + 15) / 16 * 2;
-    bandwidth_body<NT>(v, b >> 1, (int)(b & 1), keyed, sh, dyn);
+    bandwidth_body<NT>(v, b >> 1, (int)(b & 1), form, sh, dyn);
 }
 
 }  // namespace sicp

@@ -368,17 +368,20 @@ def test_bandwidth_selection_degenerate_particle_sets(kind):
 
 @pytest.mark.parametrize("K,kind", [(K, kind) for K in (120, 300)
                                     for kind in ("uniform", "identical", "two_clusters", "near_duplicates",
-                                                 "few_values")] + [(133, "uniform"), (134, "uniform")])
+                                                 "few_values")] +
+                         [(133, "uniform"), (134, "uniform"), (400, "uniform"), (400, "few_values")])
 def test_bandwidths_beside_the_screen_search_equal_the_gradient_launch(kind, K):
     """With a screen and few particles in flight the median bandwidths run
     as extra workgroups of the nearest-neighbour launch, on its workgroup
     size (256, 512 or 1024 threads): h equals the gradient launch's (FP32
     search, 1024 threads) bit for bit and the oracle's, and the iteration's
     particles are the same, on degenerate particle sets too. K = 120 keeps
-    the pair keys in LDS there; K = 300 (the LiDAR particle count) keeps the
-    distances in global memory there, while the gradient launch keys them.
-    K = 133 is the largest K whose keys fit the 48 KB there, K = 134 the
-    smallest that takes global memory."""
+    the pair keys in LDS there; K = 300 (the LiDAR particle count) keeps
+    them in global memory there, while the gradient launch keys them in
+    LDS. K = 133 is the largest K whose keys fit the 48 KB there, K = 134
+    the smallest that takes global memory; K = 400 has too many pairs for
+    16-bit keys, and both launches select over FP64 distances in global
+    memory."""
     prob = synth.make_problem("cuboid", 13, K=K, T=2)
     if kind != "uniform":
         prob.theta0 = _theta_variant(prob, kind, np.random.default_rng(5))
