@@ -541,6 +541,43 @@ def test_bf16_screen_randomized_scales_offsets_and_near_ties(seed, mode):
     _bf16_check(q.astype(np.float32), ref.astype(np.float32), mode)
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_screen_two_block_keys_randomized_scales_offsets_and_near_ties(seed):
+    """The randomized clouds above (scales 0.1 to 100 m, centres up to 300 m,
+    jittered duplicate references, queries next to references), searched
+    with keys over two blocks (two queries per lane, a chunk of 192 blocks
+    per wavefront): the first iteration's matches of both screens equal the
+    FP32 search's bit for bit."""
+    rng = np.random.default_rng(1900 + seed)
+    scale = 10.0 ** rng.uniform(-1, 2)
+    centre = rng.uniform(-1, 1, 3) * 10.0 ** rng.uniform(0, 2.5)
+    M = int(rng.integers(2000, 30000))
+    ref = centre + rng.uniform(-scale, scale, (M, 3))
+    dup = rng.choice(M, M // 5, replace=False)
+    half = len(dup) // 2
+    ref[dup[:half]] = ref[dup[half:2 * half]] + rng.normal(0, 1e-6 * scale, (half, 3))
+    K, m = 8, 400
+    src = ref[rng.choice(M, 1000, replace=False)] - centre + rng.normal(0, 1e-3 * scale, (1000, 3))
+    theta0 = np.zeros((K, 6))
+    theta0[:, :3] = centre + rng.normal(0, 0.01 * scale, (K, 3))
+    theta0[:, 3:] = rng.normal(0, 0.02, (K, 3))
+    sched = synth.minibatch_schedule(seed, len(src), m, 1)
+    src, ref = src.astype(np.float32), ref.astype(np.float32)
+    matches = {}
+    for mode in (S.NN_FP32, S.NN_F16_RERANK, S.NN_BF16_RERANK):
+        cfg = S.stein_icp_default_config(num_particles=K, batch_size=m, schedule_rows=1, autotune=0, nn_mode=mode)
+        sol = S.SteinICP(cfg, dev(src), dev(ref), dev(theta0), dev(sched))
+        try:
+            if mode != S.NN_FP32:
+                sol.set_tiling(2, 4, 32 * 4 * TWO_BLOCK_KEY_RANGE)
+            sol.step(1)
+            matches[mode] = sol.diagnostics()["match"].cpu().numpy()
+        finally:
+            sol.close()
+    for mode in (S.NN_F16_RERANK, S.NN_BF16_RERANK):
+        np.testing.assert_array_equal(matches[mode], matches[S.NN_FP32], err_msg=f"mode {mode}")
+
+
 def _grid_problem():
     """Cloud pair on an integer grid with repeated references: many exact
     ties between and inside the screen's 32-reference blocks."""
