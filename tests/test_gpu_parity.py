@@ -745,6 +745,29 @@ def test_lidar_full_size_iteration_at_the_bench_shape(nn):
     np.testing.assert_allclose(th, st.theta, rtol=0, atol=1e-11)
 
 
+@pytest.mark.parametrize("K", [40, 150, 240])
+def test_batched_bandwidths_beside_the_screen_search(K):
+    """A few pairs with few particles in flight (pairs x K <= 512) take the
+    bandwidth workgroups of every pair into the screen launch: keys in LDS
+    (K = 40), keys in global memory (K = 150, 240). Each pair's bandwidths
+    and the particles after the solve equal the FP32 batch's bit for bit."""
+    probs = synth.batched_problems(2, K=K, m=40, T=6, size_scale=0.3)
+    out = {}
+    for mode in (S.NN_FP32, S.NN_F16_RERANK, S.NN_BF16_RERANK):
+        gcfg, _ = both_configs(probs[0])
+        gcfg.nn_mode = mode
+        b = S.SteinICP.batch(gcfg, [dev(p.pair.src) for p in probs], [dev(p.pair.ref) for p in probs],
+                             dev(np.stack([p.theta0 for p in probs])), [dev(p.schedule) for p in probs])
+        try:
+            b.step(6)
+            out[mode] = (b.diagnostics()["h"].cpu().numpy(), b.particles().cpu().numpy())
+        finally:
+            b.close()
+    for mode in (S.NN_F16_RERANK, S.NN_BF16_RERANK):
+        np.testing.assert_array_equal(out[mode][0], out[S.NN_FP32][0], err_msg=f"h, mode {mode}")
+        np.testing.assert_array_equal(out[mode][1], out[S.NN_FP32][1], err_msg=f"particles, mode {mode}")
+
+
 def test_batched_uneven_pairs_bf16_equals_fp32_bitwise():
     """Uneven pairs in one batch: both certified screens give the FP32
     search's particles bit for bit."""
