@@ -477,6 +477,28 @@ def _bf16_check(q, ref, mode=S.NN_BF16_RERANK):
     np.testing.assert_array_equal(d2.view(np.uint32), od.astype(np.float32).view(np.uint32))
 
 
+@pytest.mark.parametrize("mode", [S.NN_FP32] + SCREENS)
+def test_nn_empty_single_and_ragged_sizes(mode):
+    """Edge sizes of the stand-alone search: no queries (an empty answer),
+    a single reference, references and queries one either side of the
+    32-reference blocks and 64-query work items; answers equal the oracle's
+    bit for bit. No references is refused."""
+    rng = np.random.default_rng(61)
+    idx, d2 = S.stein_icp_nn(dev(np.zeros((0, 3), np.float32)), dev(rng.normal(size=(5, 3)).astype(np.float32)),
+                             mode=mode)
+    assert idx.numel() == 0 and d2.numel() == 0
+    with pytest.raises(S.SteinICPError):
+        S.stein_icp_nn(dev(np.zeros((4, 3), np.float32)), dev(np.zeros((0, 3), np.float32)), mode=mode)
+    for n_ref in (1, 31, 32, 33, 100):
+        for nq in (1, 63, 64, 65, 129):
+            ref = rng.normal(size=(n_ref, 3)).astype(np.float32)
+            q = rng.normal(size=(nq, 3)).astype(np.float32)
+            idx, d2 = S.stein_icp_nn(dev(q), dev(ref), mode=mode)
+            oi, od = oracle.nn_f32(q, ref)
+            np.testing.assert_array_equal(idx.cpu().numpy(), oi, err_msg=f"n_ref {n_ref} nq {nq}")
+            np.testing.assert_array_equal(d2.cpu().numpy().view(np.uint32), od.astype(np.float32).view(np.uint32))
+
+
 @pytest.mark.parametrize("mode", SCREENS)
 def test_bf16_screen_kinect_queries(mode):
     prob = synth.make_problem("kinect", 0, T=1)
